@@ -1,0 +1,227 @@
+/*
+ * dmrt.h -- C ABI of libdmrt: the double-MRT thermal lattice Boltzmann time
+ * step of Z. Li, M. Yang and Y. Zhang, "Double MRT Thermal Lattice Boltzmann
+ * Method for Simulating Natural Convection of Low Prandtl Number Fluids"
+ * (arXiv:1601.04633), on AMD MI355X (gfx950).
+ *
+ * Problem (Section 2, Eqs. 1-8 and 14-17): a square cavity of side H filled
+ * with a Boussinesq fluid, left wall hot, right wall cold, top and bottom
+ * adiabatic, no slip everywhere; governed by Ra, Pr and the lattice Mach
+ * number Ma (Eq. 9).  Outputs: U, V, theta, P (Eq. 9) and the wall Nusselt
+ * number (Eqs. 18-19).
+ *
+ * Method (Section 3): per node and step, a D2Q9 MRT collision with the
+ * Boussinesq force (Eqs. 22-34), a D2Q5 MRT collision for the temperature
+ * (Eqs. 35-43), streaming, and halfway bounce-back walls (no-slip for the
+ * flow; Eq. 44 adiabatic and Eq. 45 isothermal for the temperature).
+ *
+ * Conventions shared by every call
+ *  - Lattice units: dx = dt = c = 1, c_s^2 = 1/3, rho0 = 1.  The grid has
+ *    n x n nodes; the walls lie half a link outside the outer nodes, so
+ *    H = n and node (x, y) sits at X = (x + 1/2)/n, Y = (y + 1/2)/n.
+ *  - Host field arrays are double, n*n, y-major with x fastest
+ *    (index y*n + x).  They are caller-owned.
+ *  - theta is stored shifted so that the default walls are +0.5 / -0.5;
+ *    the paper's theta (0 at the cold wall, 1 at the hot wall) is
+ *    theta + 1/2 for those defaults.
+ *  - Return value: DMRT_OK (0) or a negative error code.  No call throws.
+ *    After an error the handle stays valid unless stated otherwise.
+ *  - Threading: one host thread at a time per handle.  dmrt_step and the
+ *    set-up calls only enqueue work on the handle's stream; calls that
+ *    return host data synchronise that stream.
+ *  - Device memory: the library owns everything it allocates.  External
+ *    distribution buffers passed to dmrt_create stay owned by the caller,
+ *    who must keep them alive until dmrt_destroy.
+ *
+ * Readings of the paper that this library implements (the paper's text is
+ * garbled or silent at these places):
+ *  - Eq. 34: the energy moment equilibrium is -2 drho + 3 rho0 |u|^2.
+ *  - Eq. 37: the last row of N is (0, 1, -1, 1, -1).
+ *  - Eq. 26: F_i = 3 G.(e_i - u) f_i^eq(rho0, u)  (divisor rho0 c_s^2).
+ *  - Eq. 27: G = (force_x, gbeta (theta - theta_ref)).
+ *  - Eqs. 40/43: by default a is fixed and sigma_k solved from Eq. 43, with
+ *    sigma_e = sigma_nu from Eq. 39 (DMRT_Q5_FIXED_A); DMRT_Q5_PAPER takes
+ *    Eq. 40 literally and requires the resulting a < 1.
+ *  - Eq. 45: the anti-bounce-back constant is (4 + a)/10 theta_w.
+ *  - Eq. 18: second-order one-sided wall gradient
+ *    Nu(y) = H (8 theta_w - 9 theta(0, y) + theta(1, y)) / (3 dT).
+ */
+#ifndef DMRT_H
+#define DMRT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes */
+#define DMRT_OK           0
+#define DMRT_EINVAL      -1  /* NULL pointer, bad size or mode, non-finite input */
+#define DMRT_EUNSTABLE   -2  /* parameters outside the scheme's stable range     */
+#define DMRT_ENOMEM      -3  /* host or device allocation failed                 */
+#define DMRT_EHIP        -4  /* a HIP runtime call failed (see dmrt_last_error)   */
+#define DMRT_ENONFINITE  -5  /* the state holds NaN or Inf (watchdog)            */
+#define DMRT_ENODEV      -6  /* no usable gfx950 device                          */
+
+/* Storage and arithmetic precision of the distributions */
+#define DMRT_FP32 0
+#define DMRT_FP64 1
+
+/* D2Q5 parameterisation (Eqs. 38-43) */
+#define DMRT_Q5_FIXED_A 0   /* a given; sigma_k from Eq. 43; sigma_e = sigma_nu from Eq. 39 */
+#define DMRT_Q5_PAPER   1   /* Eq. 40 literally; a = 20 sqrt(3) alpha - 4, must be < 1     */
+
+/* Wall configuration.  CAVITY is the paper's problem; the others are test
+ * boxes that share the same kernel: PERIODIC (no walls), CHANNEL_X
+ * (periodic in x, no-slip adiabatic walls at y = 0 and y = n) and
+ * ADIABATIC_BOX (no-slip adiabatic walls on all four sides). */
+#define DMRT_BC_CAVITY        0
+#define DMRT_BC_PERIODIC      1
+#define DMRT_BC_CHANNEL_X     2
+#define DMRT_BC_ADIABATIC_BOX 3
+
+typedef struct {
+    int    n;               /* nodes per side, >= 4                                */
+    double Ra, Pr, Ma;      /* Eq. 9; all > 0                                      */
+    double theta_hot;       /* hot-wall temperature (default +0.5)                 */
+    double theta_cold;      /* cold-wall temperature (default -0.5)                */
+    int    precision;       /* DMRT_FP32 or DMRT_FP64                              */
+    int    q5_mode;         /* DMRT_Q5_FIXED_A or DMRT_Q5_PAPER                    */
+    double a;               /* D2Q5 parameter a of Eq. 42 in FIXED_A mode (-2/3)   */
+    int    bc_mode;         /* DMRT_BC_*                                           */
+    double gbeta_override;  /* NaN: g beta = Ma^2 / (3 H dT) from Eq. 9; else used */
+    double force_x;         /* constant horizontal body force (test boxes), 0      */
+    double theta_ref;       /* reference temperature of Eq. 27 (default 0)         */
+} dmrt_params;
+
+/* Derived lattice parameters (Eqs. 9, 11-13, 32, 38-43). */
+typedef struct {
+    double nu, alpha, gbeta;            /* viscosity, diffusivity, g beta            */
+    double s_nu, s_q;                   /* Eq. 32 (s_e = s_eps = s_nu)               */
+    double sigma_k, sigma_e, sigma_nu;  /* Eq. 38                                    */
+    double a;                           /* Eq. 42                                    */
+    double w0, wm;                      /* D2Q5 equilibrium weights (1-a)/5, (4+a)/20 */
+    double H;                           /* = n                                       */
+} dmrt_derived;
+
+typedef struct dmrt_cavity dmrt_cavity;   /* opaque, library-owned */
+
+/* Fill *p with the defaults: n = 64, Ra = 1e3, Pr = 0.01, Ma = 0.1, walls
+ * +-0.5, FP64, FIXED_A with a = -2/3, CAVITY, gbeta derived, no force_x,
+ * theta_ref = 0.  Returns DMRT_EINVAL if p is NULL. */
+int dmrt_params_default(dmrt_params *p);
+
+/* Parameter map of Eq. 9 / Eqs. 11-13 (H = n, c_s^2 = 1/3):
+ *   nu = Ma H sqrt(Pr / (3 Ra)), alpha = nu / Pr, g beta = Ma^2 / (3 H dT);
+ * Eq. 32 for s_nu, s_q; Eqs. 39-43 for sigma_k, sigma_e, sigma_nu and a.
+ * Host only, touches no device.  DMRT_EINVAL for NULL or non-finite input or
+ * n < 4; DMRT_EUNSTABLE for Ma, Ra or Pr <= 0, a outside (-4, 1), or any
+ * relaxation rate outside (0, 2). */
+int dmrt_derive(const dmrt_params *p, dmrt_derived *out);
+
+/* Bytes that external distribution buffers must provide for these
+ * parameters: f_bytes for both ping-pong copies of the 9 D2Q9 planes,
+ * g_bytes for both copies of the 5 D2Q5 planes.  Layout of each buffer:
+ * [copy 0..1][population][y 0..n-1][x 0..pitch-1], pitch = n rounded up to
+ * a multiple of 64 elements, element = float (FP32) or double (FP64).
+ * The stored f is the deviation from w_i rho0 (Eq. 33: sum f = drho). */
+int dmrt_buffer_bytes(const dmrt_params *p, size_t *f_bytes, size_t *g_bytes);
+
+/* Create a cavity on the current HIP device.  ext_f / ext_g: NULL to let
+ * the library allocate, or device pointers of at least dmrt_buffer_bytes
+ * bytes, 256-byte aligned (both NULL or both non-NULL).  hip_stream: the
+ * hipStream_t to enqueue on, or NULL for a library-created stream.  The
+ * state starts at rest with theta = 0 (call dmrt_set_theta to change it).
+ * Errors: EINVAL, EUNSTABLE (as dmrt_derive), ENOMEM, EHIP, ENODEV. */
+int dmrt_create(const dmrt_params *p, void *ext_f, void *ext_g, void *hip_stream,
+                dmrt_cavity **out);
+
+/* Re-initialise at rest: pre-collision f = 0 (drho = 0, u = 0) and g at the
+ * D2Q5 equilibrium of theta0 (n*n host doubles), then one collision; the
+ * step counter is reset to 0.  Enqueued; theta0 may be reused on return. */
+int dmrt_set_theta(dmrt_cavity *h, const double *theta0);
+
+/* Re-initialise at the equilibria of the given fields (Eqs. 34, 42): drho,
+ * U, V, theta are n*n host doubles, any of them NULL for zero. */
+int dmrt_set_equilibrium(dmrt_cavity *h, const double *drho, const double *U,
+                         const double *V, const double *theta);
+
+/* Hot-wall temperature per row, theta_w(y) for y = 0..n-1 (n host doubles),
+ * used by Eq. 45 on the left wall and by the hot-wall Nusselt number.
+ * Takes effect from the next step. */
+int dmrt_set_hot_wall(dmrt_cavity *h, const double *theta_w);
+
+/* Advance nsteps >= 0 time steps (Eqs. 25 and 36 with the walls).  Enqueued
+ * only; long runs replay a captured graph of the step kernel. */
+int dmrt_step(dmrt_cavity *h, long nsteps);
+
+/* Wait for all work enqueued on the handle's stream. */
+int dmrt_sync(dmrt_cavity *h);
+
+/* Steps taken since the last (re)initialisation. */
+int dmrt_get_step(dmrt_cavity *h, long *step);
+
+/* Fields at the current step (Eq. 9, Eq. 33, Eq. 41): U = u, V = v
+ * (U = u / (sqrt(3) c_s)), theta, P = drho / 3.  Any output may be NULL.
+ * Synchronises.  u is the velocity of Eq. 33 (first moment of the
+ * pre-collision populations over rho0). */
+int dmrt_get_fields(dmrt_cavity *h, double *U, double *V, double *theta, double *P);
+
+/* Wall Nusselt number (Eqs. 18-19, second-order wall gradient, midpoint
+ * rule over the n rows).  wall 0: hot wall x = 0; wall 1: cold wall x = H,
+ * where Nu = -dtheta/dX as well (heat flowing out).  nu_local: n doubles or
+ * NULL.  Synchronises. */
+int dmrt_nusselt(dmrt_cavity *h, int wall, double *nu_avg, double *nu_local);
+
+/* Record the hot-wall Nu_avg on the device every `stride` steps (counted
+ * from the last initialisation), into a ring of `cap` doubles; stride 0
+ * switches recording off.  Resets the ring. */
+int dmrt_nu_series(dmrt_cavity *h, int stride, long cap);
+
+/* Copy the recorded samples, oldest first, into out (room for cap doubles);
+ * *count receives how many were copied (at most cap; older ones are
+ * overwritten).  Synchronises. */
+int dmrt_nu_series_read(dmrt_cavity *h, double *out, long *count);
+
+/* Relative change of theta and of (U, V) since the previous call (or since
+ * initialisation): ||x_now - x_prev||_2 / ||x_now||_2, accumulated in FP64
+ * on the device, then the reference is updated.  Returns DMRT_ENONFINITE
+ * if any distribution is NaN or Inf.  Synchronises. */
+int dmrt_residual(dmrt_cavity *h, double *res_theta, double *res_u);
+
+/* Host checkpoint of the complete state (distributions at the current step,
+ * step counter, hot-wall profile).  dmrt_state_bytes gives the size;
+ * dmrt_load_state requires a blob saved with the same n and precision and
+ * resumes bitwise identically.  Both synchronise. */
+int dmrt_state_bytes(dmrt_cavity *h, size_t *bytes);
+int dmrt_save_state(dmrt_cavity *h, void *host, size_t bytes);
+int dmrt_load_state(dmrt_cavity *h, const void *host, size_t bytes);
+
+/* Launch shape of the step kernel: block_x in {64, 128, 256, 512},
+ * block_y >= 1 with block_x * block_y <= 1024, xcd_remap 0/1 (assign
+ * contiguous tiles to each of the 8 accelerator dies), graph_steps >= 0
+ * (steps per captured graph; 0 = never capture).  Defaults are set at
+ * creation; results do not depend on the launch shape. */
+int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
+                    int graph_steps);
+
+/* Device pointers of the two ping-pong copies and the index (0/1) of the
+ * copy holding the current state; for callers that manage memory. */
+int dmrt_buffers(dmrt_cavity *h, void **f, void **g, int *current);
+
+/* Release the handle and the device memory the library allocated.  Waits
+ * for pending work.  NULL is accepted. */
+int dmrt_destroy(dmrt_cavity *h);
+
+/* Static description of an error code. */
+const char *dmrt_strerror(int code);
+
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char *dmrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMRT_H */
