@@ -1,0 +1,187 @@
+"""Benchmark of the double-MRT thermal LBM time step on one MI355X.
+
+A "step" is one time step of the whole hot path over one cavity: pull
+streaming with the wall conditions, D2Q9 MRT collision with buoyancy, D2Q5
+MRT collision and the store (one fused kernel launch).  Default workload:
+the 1024 x 1024 cavity, Ra = 1e5, Pr = 0.001, Ma = 0.1, FP32 storage and
+arithmetic, seeded noise initial temperature (synthetic; the paper has no
+dataset).
+
+Prints ONE JSON line.  value = MLUPS (million node updates per second, one
+node update = one D2Q9 + one D2Q5 node advanced one step) with the state
+resident in HBM before the timed region starts.
+
+python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (D2Q9+D2Q5 node updates/s), % HBM roofline; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD published)
+WORDS_PER_NODE = 28            # 14 populations read + 14 written per node update
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_04633_amd", "csrc", f)
+                  for f in ("dmrt_device.hpp",)]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(bytes_alg_per_launch):
+    """HBM bytes per launch from the committed counter summary, or None when
+    it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601):
+    """Returns (ms total, MLUPS, avg ms per launch) for `steps` steps timed
+    with HIP events on the cavity's own stream."""
+    import torch
+    from paper_1601_04633_amd import inputs
+    from paper_1601_04633_amd.dmrt import Cavity
+    stream = torch.cuda.Stream()
+    c = Cavity(n=n, Ra=Ra, Pr=Pr, precision=precision, stream=stream.cuda_stream)
+    if launch:
+        c.set_launch(*launch)
+    c.set_theta(inputs.theta_noise(n, seed))
+    c.step(warmup)
+    c.sync()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    c.step(steps)
+    t1.record(stream)
+    t1.synchronize()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    nu = c.nusselt(0)[0]
+    c.close()
+    mlups = n * n * steps / (ms * 1e-3) / 1e6
+    return ms, mlups, ms / steps, nu
+
+
+def cpu_baseline(n, Ra, Pr, budget_s=15.0):
+    """The FP64 oracle on the host (single thread) over a bounded sample of
+    the same workload: whole steps of the same cavity until ~budget_s."""
+    from oracle import oracle as orc
+    from paper_1601_04633_amd import inputs
+    o = orc.Oracle(n, Ra, Pr)
+    o.set_theta(inputs.theta_noise(n, 1601))
+    t = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t
+    k = max(1, int(budget_s / max(one, 1e-9)) - 1)
+    t = time.perf_counter()
+    o.step(k)
+    el = time.perf_counter() - t
+    return {"value": round(n * n * k / el / 1e6, 4), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{k} steps of the {n}x{n} cavity (Ra={Ra:g}, Pr={Pr:g}, FP64, "
+                      f"single thread), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--Ra", type=float, default=1e5)
+    ap.add_argument("--Pr", type=float, default=0.001)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--launch", default="", help="block_x,block_y,xcd_remap,graph_steps")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the cavity path is single-GPU in this build "
+              "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+
+    n, Ra, Pr, prec = args.n, args.Ra, args.Pr, args.precision
+    log(f"main: {n}^2 Ra={Ra:g} Pr={Pr:g} {prec} steps={args.steps} warmup={args.warmup}")
+    ms, mlups, ms_launch, nu = time_cavity(n, Ra, Pr, prec, args.steps, args.warmup, launch)
+    esz = 8 if prec == "fp64" else 4
+    alg_bytes = WORDS_PER_NODE * esz * n * n
+    achieved = alg_bytes / (ms_launch * 1e-3) / 1e9
+    traffic = measured_traffic(alg_bytes) if (n == 1024 and prec == "fp32" and not launch) else None
+    log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s, {ms_launch*1e3:.2f} us/launch, Nu {nu:.5f}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32",
+        "data": "synthetic: seeded uniform noise of amplitude 1e-4 on theta at rest (numpy PCG64, seed 1601)",
+        "config": {"workload": f"differentially heated cavity {n}x{n}, Ra={Ra:g}, Pr={Pr:g}, "
+                               f"Ma=0.1, walls +-0.5, {prec.upper()} fused collide-stream step",
+                   "global_batch": 1, "nodes": n * n, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "step_kernel<float, BC_CAVITY>",
+                     "bytes_per_node_update": WORDS_PER_NODE * esz},
+        "nu_hot_wall": nu,
+    }
+
+    if not args.no_extras:
+        extras = {}
+        log("extra: fp64 same cavity")
+        _, m64, l64, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1000), 500)
+        extras["fp64_mlups"] = round(m64, 1)
+        extras["fp64_hbm_frac"] = round(224 * n * n / (l64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        log("extra: 2048^2 fp32 control (state larger than the 256 MB last-level cache)")
+        _, m2k, l2k, _ = time_cavity(2048, Ra, Pr, "fp32", 5000, 500)
+        extras["fp32_2048_mlups"] = round(m2k, 1)
+        extras["fp32_2048_hbm_frac"] = round(112 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        out["extras"] = extras
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle, single thread)")
+        out["cpu_baseline"] = cpu_baseline(n, Ra, Pr)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,790 @@
+// dmrt_host.hip -- host side of libdmrt: the C ABI declared in include/dmrt.h.
+//
+// Owns parameters, device buffers, the stream, the captured step graphs and
+// the diagnostics scratch of one cavity.  Every entry point returns an error
+// code; HIP failures are recorded per thread for dmrt_last_error().
+#include "dmrt.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dmrt_device.hpp"
+#include "dmrt_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+}  // namespace
+
+namespace dmrt {
+
+int record_hip(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return DMRT_OK;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    g_last_error = buf;
+    if (e == hipErrorOutOfMemory) return DMRT_ENOMEM;
+    if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return DMRT_ENODEV;
+    return DMRT_EHIP;
+}
+
+// Parameter map (Eq. 9 with Eqs. 11-13; Eq. 32; Eqs. 38-43).
+int derive(const dmrt_params* p, dmrt_derived* d)
+{
+    if (!p || !d) return DMRT_EINVAL;
+    if (p->n < 4 || p->n > 32768) return DMRT_EINVAL;
+    const double vals[] = {p->Ra, p->Pr, p->Ma, p->theta_hot, p->theta_cold, p->force_x,
+                           p->theta_ref};
+    for (double v : vals)
+        if (!std::isfinite(v)) return DMRT_EINVAL;
+    if (p->precision != DMRT_FP32 && p->precision != DMRT_FP64) return DMRT_EINVAL;
+    if (p->bc_mode < DMRT_BC_CAVITY || p->bc_mode > DMRT_BC_ADIABATIC_BOX) return DMRT_EINVAL;
+    if (!(p->Ra > 0.0) || !(p->Pr > 0.0) || !(p->Ma > 0.0)) return DMRT_EUNSTABLE;
+    const double H = p->n;
+    const double dT = p->theta_hot - p->theta_cold;
+    double gbeta;
+    if (std::isnan(p->gbeta_override)) {
+        if (!(dT > 0.0)) return DMRT_EINVAL;
+        // u_c^2 = g beta dT H = Ma^2 c_s^2
+        gbeta = p->Ma * p->Ma / (3.0 * H * dT);
+    } else {
+        if (!std::isfinite(p->gbeta_override)) return DMRT_EINVAL;
+        gbeta = p->gbeta_override;
+    }
+    const double nu = p->Ma * H * std::sqrt(p->Pr / (3.0 * p->Ra));
+    const double alpha = nu / p->Pr;
+    const double s_nu = 2.0 / (6.0 * nu + 1.0);
+    const double s_q = 8.0 * (2.0 - s_nu) / (8.0 - s_nu);
+    double a, sk, se;
+    if (p->q5_mode == DMRT_Q5_PAPER) {
+        const double lk = std::sqrt(3.0) / 6.0;       // Eq. 40
+        sk = 1.0 / (0.5 + lk);
+        se = 1.0 / (0.5 + std::sqrt(3.0) / 3.0);
+        a = 10.0 * alpha / lk - 4.0;                   // Eq. 43 solved for a
+    } else if (p->q5_mode == DMRT_Q5_FIXED_A) {
+        if (!std::isfinite(p->a)) return DMRT_EINVAL;
+        a = p->a;
+        if (!(a > -4.0)) return DMRT_EUNSTABLE;
+        const double lk = 10.0 * alpha / (4.0 + a);   // Eq. 43 solved for sigma_k
+        sk = 1.0 / (0.5 + lk);
+        se = 1.0 / (0.5 + 1.0 / (6.0 * lk));           // Eq. 39
+    } else {
+        return DMRT_EINVAL;
+    }
+    if (!(a > -4.0 && a < 1.0)) return DMRT_EUNSTABLE;
+    const double rates[] = {s_nu, s_q, sk, se};
+    for (double r : rates)
+        if (!(r > 0.0 && r < 2.0)) return DMRT_EUNSTABLE;
+    d->nu = nu; d->alpha = alpha; d->gbeta = gbeta;
+    d->s_nu = s_nu; d->s_q = s_q;
+    d->sigma_k = sk; d->sigma_e = se; d->sigma_nu = se;
+    d->a = a; d->w0 = (1.0 - a) / 5.0; d->wm = (4.0 + a) / 20.0; d->H = H;
+    return DMRT_OK;
+}
+
+int pitch_of(int n) { return (n + 63) / 64 * 64; }
+
+}  // namespace dmrt
+
+using namespace dmrt;
+
+#define HIPCHK(expr)                                        \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return record_hip(e_, #expr); \
+    } while (0)
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+size_t elem_size(int precision) { return precision == DMRT_FP64 ? sizeof(double) : sizeof(float); }
+
+template <typename real>
+Coef<real> make_coef(const dmrt_params& p, const dmrt_derived& d)
+{
+    Coef<real> c;
+    c.s_nu = real(d.s_nu); c.s_q = real(d.s_q);
+    c.sk = real(d.sigma_k); c.se = real(d.sigma_e); c.sn = real(d.sigma_nu);
+    c.a = real(d.a);
+    c.cabb = real((4.0 + d.a) / 10.0);
+    c.gbeta = real(d.gbeta);
+    c.gy0 = real(-d.gbeta * p.theta_ref);
+    c.gx = real(p.force_x);
+    c.cold = real((4.0 + d.a) / 10.0 * p.theta_cold);
+    return c;
+}
+
+}  // namespace
+
+struct dmrt_cavity {
+    dmrt_params p;
+    dmrt_derived d;
+    int dev = 0;
+    int n = 0, pitch = 0, plane = 0;
+    size_t esz = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    void* fbuf = nullptr;     // [2][9][plane]
+    void* gbuf = nullptr;     // [2][5][plane]
+    bool own_bufs = false;
+    int cur = 0;              // copy holding the current state
+    long step = 0;
+    // hot wall
+    void* thw_real = nullptr;         // n reals
+    double* thw_dbl = nullptr;        // n doubles
+    std::vector<double> thw_host;
+    // diagnostics scratch
+    double* scratch = nullptr;        // fields upload / download, 4 n^2 doubles
+    double* nu_buf = nullptr;         // n + 1 doubles
+    double* res_ref = nullptr;        // 3 n^2 doubles
+    double* res_part = nullptr;       // residual partials
+    int res_blocks = 0;
+    double* ring = nullptr;
+    unsigned long long* ring_count = nullptr;
+    long ring_cap = 0;
+    int series_stride = 0;
+    // launch
+    int block_x = 256, block_y = 1, xcd_remap = 1, graph_steps = 64;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraph_t graph_def[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+void drop_graphs(dmrt_cavity* h)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (h->graph[i]) (void)hipGraphExecDestroy(h->graph[i]);
+        if (h->graph_def[i]) (void)hipGraphDestroy(h->graph_def[i]);
+        h->graph[i] = nullptr;
+        h->graph_def[i] = nullptr;
+    }
+}
+
+template <typename real>
+real* fptr(dmrt_cavity* h, int copy) { return static_cast<real*>(h->fbuf) + (size_t)copy * 9 * h->plane; }
+template <typename real>
+real* gptr(dmrt_cavity* h, int copy) { return static_cast<real*>(h->gbuf) + (size_t)copy * 5 * h->plane; }
+
+template <typename real>
+int launch_step_t(dmrt_cavity* h, hipStream_t s, int from)
+{
+    StepArgs<real> A;
+    A.fin = fptr<real>(h, from);
+    A.gin = gptr<real>(h, from);
+    A.fout = fptr<real>(h, from ^ 1);
+    A.gout = gptr<real>(h, from ^ 1);
+    A.thw = static_cast<const real*>(h->thw_real);
+    A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
+    A.tiles_x = (h->n + h->block_x - 1) / h->block_x;
+    const int tiles_y = (h->n + h->block_y - 1) / h->block_y;
+    A.tiles = A.tiles_x * tiles_y;
+    A.xcd_remap = h->xcd_remap;
+    A.c = make_coef<real>(h->p, h->d);
+    int nblocks = A.tiles;
+    if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
+    dim3 grid(nblocks), block(h->block_x, h->block_y);
+    switch (h->p.bc_mode) {
+    case DMRT_BC_CAVITY: hipLaunchKernelGGL((step_kernel<real, BC_CAVITY>), grid, block, 0, s, A); break;
+    case DMRT_BC_PERIODIC: hipLaunchKernelGGL((step_kernel<real, BC_PERIODIC>), grid, block, 0, s, A); break;
+    case DMRT_BC_CHANNEL_X: hipLaunchKernelGGL((step_kernel<real, BC_CHANNEL_X>), grid, block, 0, s, A); break;
+    default: hipLaunchKernelGGL((step_kernel<real, BC_ADIABATIC_BOX>), grid, block, 0, s, A); break;
+    }
+    HIPCHK(hipGetLastError());
+    return DMRT_OK;
+}
+
+int launch_step(dmrt_cavity* h, hipStream_t s, int from)
+{
+    return h->esz == sizeof(double) ? launch_step_t<double>(h, s, from)
+                                    : launch_step_t<float>(h, s, from);
+}
+
+template <typename real>
+int launch_nusselt_t(dmrt_cavity* h, hipStream_t s, int copy, int wall, double* local,
+                     double* avg, bool to_ring)
+{
+    const double dT = h->p.theta_hot - h->p.theta_cold;
+    const double inv_dT = dT != 0.0 ? 1.0 / dT : 1.0;
+    hipLaunchKernelGGL((nusselt_kernel<real>), dim3(1), dim3(256), 0, s, gptr<real>(h, copy),
+                       h->n, h->pitch, h->plane, wall, h->thw_dbl, h->p.theta_cold, h->d.H, inv_dT,
+                       local, avg, to_ring ? h->ring : nullptr, h->ring_count, h->ring_cap);
+    HIPCHK(hipGetLastError());
+    return DMRT_OK;
+}
+
+int launch_nusselt(dmrt_cavity* h, hipStream_t s, int copy, int wall, double* local, double* avg,
+                   bool to_ring)
+{
+    return h->esz == sizeof(double) ? launch_nusselt_t<double>(h, s, copy, wall, local, avg, to_ring)
+                                    : launch_nusselt_t<float>(h, s, copy, wall, local, avg, to_ring);
+}
+
+// Enqueue `count` steps starting at copy `from` with Nu samples where due;
+// `base` is the step counter before the first of them.
+int enqueue_steps(dmrt_cavity* h, hipStream_t s, int from, long base, long count)
+{
+    int c = from;
+    for (long i = 0; i < count; ++i) {
+        int rc = launch_step(h, s, c);
+        if (rc) return rc;
+        c ^= 1;
+        if (h->series_stride > 0 && (base + i + 1) % h->series_stride == 0) {
+            rc = launch_nusselt(h, s, c, 0, nullptr, nullptr, true);
+            if (rc) return rc;
+        }
+    }
+    return DMRT_OK;
+}
+
+int graph_unit(const dmrt_cavity* h)
+{
+    // steps per graph: even (returns to the same copy) and a multiple of the
+    // Nu sampling stride, so that replays stay aligned with the samples
+    long k = h->graph_steps;
+    if (k <= 0) return 0;
+    if (k % 2) ++k;
+    if (h->series_stride > 0) {
+        long s = h->series_stride;
+        long l = (s % 2) ? 2 * s : s;
+        k = (k + l - 1) / l * l;
+    }
+    return (int)k;
+}
+
+int build_graph(dmrt_cavity* h, int parity, int unit)
+{
+    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_steps(h, h->cap_stream, parity, 0, unit);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return record_hip(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return record_hip(e, "hipGraphInstantiate"); }
+    h->graph_def[parity] = g;
+    h->graph[parity] = ge;
+    return DMRT_OK;
+}
+
+int upload_hot_wall(dmrt_cavity* h)
+{
+    const int n = h->n;
+    HIPCHK(hipMemcpyAsync(h->thw_dbl, h->thw_host.data(), n * sizeof(double),
+                          hipMemcpyHostToDevice, h->stream));
+    if (h->esz == sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(h->thw_real, h->thw_host.data(), n * sizeof(double),
+                              hipMemcpyHostToDevice, h->stream));
+    } else {
+        std::vector<float> tmp(n);
+        for (int i = 0; i < n; ++i) tmp[i] = (float)h->thw_host[i];
+        HIPCHK(hipMemcpyAsync(h->thw_real, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice,
+                              h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+template <typename real>
+int launch_init_t(dmrt_cavity* h, const double* dr, const double* U, const double* V,
+                  const double* T)
+{
+    const dim3 block(64, 4), grid((h->n + 63) / 64, (h->n + 3) / 4);
+    hipLaunchKernelGGL((init_kernel<real>), grid, block, 0, h->stream, fptr<real>(h, 0),
+                       gptr<real>(h, 0), dr, U, V, T, h->n, h->pitch, h->plane,
+                       make_coef<real>(h->p, h->d), real(h->d.w0), real(h->d.wm));
+    HIPCHK(hipGetLastError());
+    return DMRT_OK;
+}
+
+int ensure_scratch(dmrt_cavity* h)
+{
+    if (!h->scratch) {
+        const size_t nn = (size_t)h->n * h->n;
+        HIPCHK(hipMalloc(&h->scratch, 4 * nn * sizeof(double)));
+    }
+    return DMRT_OK;
+}
+
+int check_host_array(const double* a, size_t count)
+{
+    if (!a) return DMRT_OK;
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(a[i])) return DMRT_EINVAL;
+    return DMRT_OK;
+}
+
+int reset_series(dmrt_cavity* h)
+{
+    if (h->ring_count) HIPCHK(hipMemsetAsync(h->ring_count, 0, sizeof(unsigned long long), h->stream));
+    return DMRT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int dmrt_params_default(dmrt_params* p)
+{
+    if (!p) return DMRT_EINVAL;
+    p->n = 64;
+    p->Ra = 1e3; p->Pr = 0.01; p->Ma = 0.1;
+    p->theta_hot = 0.5; p->theta_cold = -0.5;
+    p->precision = DMRT_FP64;
+    p->q5_mode = DMRT_Q5_FIXED_A;
+    p->a = -2.0 / 3.0;
+    p->bc_mode = DMRT_BC_CAVITY;
+    p->gbeta_override = NAN;
+    p->force_x = 0.0;
+    p->theta_ref = 0.0;
+    return DMRT_OK;
+}
+
+int dmrt_derive(const dmrt_params* p, dmrt_derived* out) { return derive(p, out); }
+
+int dmrt_buffer_bytes(const dmrt_params* p, size_t* f_bytes, size_t* g_bytes)
+{
+    dmrt_derived d;
+    int rc = derive(p, &d);
+    if (rc) return rc;
+    const size_t plane = (size_t)p->n * pitch_of(p->n);
+    const size_t e = elem_size(p->precision);
+    if (f_bytes) *f_bytes = 2 * 9 * plane * e;
+    if (g_bytes) *g_bytes = 2 * 5 * plane * e;
+    return DMRT_OK;
+}
+
+int dmrt_destroy(dmrt_cavity* h);
+
+int dmrt_create(const dmrt_params* p, void* ext_f, void* ext_g, void* hip_stream,
+                dmrt_cavity** out)
+{
+    if (!out) return DMRT_EINVAL;
+    *out = nullptr;
+    dmrt_derived d;
+    int rc = derive(p, &d);
+    if (rc) return rc;
+    if ((ext_f == nullptr) != (ext_g == nullptr)) return DMRT_EINVAL;
+    if ((ext_f && ((uintptr_t)ext_f % 256)) || (ext_g && ((uintptr_t)ext_g % 256))) return DMRT_EINVAL;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_last_error = std::string("device is ") + prop.gcnArchName + ", not gfx950";
+        return DMRT_ENODEV;
+    }
+    dmrt_cavity* h = new (std::nothrow) dmrt_cavity();
+    if (!h) return DMRT_ENOMEM;
+    h->p = *p;
+    h->d = d;
+    h->dev = dev;
+    h->n = p->n;
+    h->pitch = pitch_of(p->n);
+    h->plane = h->n * h->pitch;
+    h->esz = elem_size(p->precision);
+    h->thw_host.assign(h->n, p->theta_hot);
+    auto fail = [&](int code) { dmrt_destroy(h); return code; };
+    hipError_t e;
+    if (hip_stream) {
+        h->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(record_hip(e, "hipStreamCreate"));
+        h->own_stream = true;
+    }
+    e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(record_hip(e, "hipStreamCreate(capture)"));
+    const size_t fbytes = 2 * 9 * (size_t)h->plane * h->esz;
+    const size_t gbytes = 2 * 5 * (size_t)h->plane * h->esz;
+    if (ext_f) {
+        h->fbuf = ext_f;
+        h->gbuf = ext_g;
+    } else {
+        if ((e = hipMalloc(&h->fbuf, fbytes)) != hipSuccess) return fail(record_hip(e, "hipMalloc(f)"));
+        if ((e = hipMalloc(&h->gbuf, gbytes)) != hipSuccess) return fail(record_hip(e, "hipMalloc(g)"));
+        h->own_bufs = true;
+    }
+    // padding columns are never read or written by the kernels; clear them
+    // once so that checkpoints and counters see defined memory
+    if ((e = hipMemsetAsync(h->fbuf, 0, fbytes, h->stream)) != hipSuccess) return fail(record_hip(e, "memset f"));
+    if ((e = hipMemsetAsync(h->gbuf, 0, gbytes, h->stream)) != hipSuccess) return fail(record_hip(e, "memset g"));
+    if ((e = hipMalloc(&h->thw_real, h->n * h->esz)) != hipSuccess) return fail(record_hip(e, "hipMalloc(thw)"));
+    if ((e = hipMalloc(&h->thw_dbl, h->n * sizeof(double))) != hipSuccess) return fail(record_hip(e, "hipMalloc(thw)"));
+    if ((e = hipMalloc(&h->nu_buf, (h->n + 1) * sizeof(double))) != hipSuccess) return fail(record_hip(e, "hipMalloc(nu)"));
+    if ((rc = upload_hot_wall(h))) return fail(rc);
+    *out = h;
+    rc = dmrt_set_theta(h, nullptr);
+    if (rc) { *out = nullptr; return fail(rc); }
+    return DMRT_OK;
+}
+
+int dmrt_set_equilibrium(dmrt_cavity* h, const double* drho, const double* U, const double* V,
+                         const double* theta)
+{
+    if (!h) return DMRT_EINVAL;
+    const size_t nn = (size_t)h->n * h->n;
+    const double* src[4] = {drho, U, V, theta};
+    for (auto a : src)
+        if (check_host_array(a, nn)) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    if (!g.ok) return record_hip(hipErrorInvalidDevice, "hipSetDevice");
+    int rc = ensure_scratch(h);
+    if (rc) return rc;
+    const double* dptr[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int i = 0; i < 4; ++i) {
+        if (!src[i]) continue;
+        double* dst = h->scratch + i * nn;
+        HIPCHK(hipMemcpyAsync(dst, src[i], nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        dptr[i] = dst;
+    }
+    rc = h->esz == sizeof(double) ? launch_init_t<double>(h, dptr[0], dptr[1], dptr[2], dptr[3])
+                                  : launch_init_t<float>(h, dptr[0], dptr[1], dptr[2], dptr[3]);
+    if (rc) return rc;
+    h->cur = 0;
+    h->step = 0;
+    if ((rc = reset_series(h))) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_set_theta(dmrt_cavity* h, const double* theta0)
+{
+    return dmrt_set_equilibrium(h, nullptr, nullptr, nullptr, theta0);
+}
+
+int dmrt_set_hot_wall(dmrt_cavity* h, const double* theta_w)
+{
+    if (!h || !theta_w) return DMRT_EINVAL;
+    if (check_host_array(theta_w, h->n)) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    h->thw_host.assign(theta_w, theta_w + h->n);
+    return upload_hot_wall(h);
+}
+
+int dmrt_step(dmrt_cavity* h, long nsteps)
+{
+    if (!h || nsteps < 0) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    if (!g.ok) return record_hip(hipErrorInvalidDevice, "hipSetDevice");
+    const int unit = graph_unit(h);
+    long left = nsteps;
+    while (left > 0) {
+        const bool aligned = unit > 0 && (h->step % unit) == 0;
+        if (aligned && left >= unit) {
+            if (!h->graph[h->cur]) {
+                int rc = build_graph(h, h->cur, unit);
+                if (rc) return rc;
+            }
+            const long reps = left / unit;
+            for (long r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(h->graph[h->cur], h->stream));
+            h->step += reps * unit;      // unit is even: cur is unchanged
+            left -= reps * unit;
+        } else {
+            long chunk = left;
+            if (unit > 0) {
+                const long to_align = unit - (h->step % unit);
+                if (to_align < chunk) chunk = to_align;
+            }
+            int rc = enqueue_steps(h, h->stream, h->cur, h->step, chunk);
+            if (rc) return rc;
+            h->step += chunk;
+            if (chunk & 1) h->cur ^= 1;
+            left -= chunk;
+        }
+    }
+    return DMRT_OK;
+}
+
+int dmrt_sync(dmrt_cavity* h)
+{
+    if (!h) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_get_step(dmrt_cavity* h, long* step)
+{
+    if (!h || !step) return DMRT_EINVAL;
+    *step = h->step;
+    return DMRT_OK;
+}
+
+int dmrt_get_fields(dmrt_cavity* h, double* U, double* V, double* theta, double* P)
+{
+    if (!h) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    int rc = ensure_scratch(h);
+    if (rc) return rc;
+    const size_t nn = (size_t)h->n * h->n;
+    double* s = h->scratch;
+    const dim3 block(64, 4), grid((h->n + 63) / 64, (h->n + 3) / 4);
+    const double gy0 = -h->d.gbeta * h->p.theta_ref;
+    if (h->esz == sizeof(double)) {
+        hipLaunchKernelGGL((fields_kernel<double>), grid, block, 0, h->stream, fptr<double>(h, h->cur),
+                           gptr<double>(h, h->cur), h->n, h->pitch, h->plane, h->d.gbeta, gy0,
+                           h->p.force_x, s, s + nn, s + 2 * nn, s + 3 * nn);
+    } else {
+        // FP32 storage: coefficients rounded as the step kernel rounds them
+        hipLaunchKernelGGL((fields_kernel<float>), grid, block, 0, h->stream, fptr<float>(h, h->cur),
+                           gptr<float>(h, h->cur), h->n, h->pitch, h->plane,
+                           (double)(float)h->d.gbeta, (double)(float)gy0, (double)(float)h->p.force_x,
+                           s, s + nn, s + 2 * nn, s + 3 * nn);
+    }
+    HIPCHK(hipGetLastError());
+    double* outs[4] = {U, V, theta, P};
+    for (int i = 0; i < 4; ++i)
+        if (outs[i])
+            HIPCHK(hipMemcpyAsync(outs[i], s + i * nn, nn * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_nusselt(dmrt_cavity* h, int wall, double* nu_avg, double* nu_local)
+{
+    if (!h || (wall != 0 && wall != 1)) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    int rc = launch_nusselt(h, h->stream, h->cur, wall, h->nu_buf + 1, h->nu_buf, false);
+    if (rc) return rc;
+    if (nu_avg) HIPCHK(hipMemcpyAsync(nu_avg, h->nu_buf, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (nu_local)
+        HIPCHK(hipMemcpyAsync(nu_local, h->nu_buf + 1, h->n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_nu_series(dmrt_cavity* h, int stride, long cap)
+{
+    if (!h || stride < 0 || (stride > 0 && cap <= 0)) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    if (h->ring) { (void)hipFree(h->ring); h->ring = nullptr; }
+    h->ring_cap = 0;
+    h->series_stride = stride;
+    if (stride == 0) return DMRT_OK;
+    if (!h->ring_count) HIPCHK(hipMalloc(&h->ring_count, sizeof(unsigned long long)));
+    HIPCHK(hipMalloc(&h->ring, cap * sizeof(double)));
+    h->ring_cap = cap;
+    int rc = reset_series(h);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_nu_series_read(dmrt_cavity* h, double* out, long* count)
+{
+    if (!h || !count) return DMRT_EINVAL;
+    *count = 0;
+    if (!h->ring) return DMRT_OK;
+    DeviceGuard g(h->dev);
+    unsigned long long c = 0;
+    HIPCHK(hipMemcpyAsync(&c, h->ring_count, sizeof c, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const unsigned long long cap = (unsigned long long)h->ring_cap;
+    const unsigned long long have = c < cap ? c : cap;
+    if (have && !out) return DMRT_EINVAL;
+    std::vector<double> tmp(h->ring_cap);
+    HIPCHK(hipMemcpyAsync(tmp.data(), h->ring, cap * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const unsigned long long first = c - have;
+    for (unsigned long long i = 0; i < have; ++i) out[i] = tmp[(first + i) % cap];
+    *count = (long)have;
+    return DMRT_OK;
+}
+
+int dmrt_residual(dmrt_cavity* h, double* res_theta, double* res_u)
+{
+    if (!h) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    const size_t nn = (size_t)h->n * h->n;
+    if (!h->res_ref) {
+        HIPCHK(hipMalloc(&h->res_ref, 3 * nn * sizeof(double)));
+        HIPCHK(hipMemsetAsync(h->res_ref, 0, 3 * nn * sizeof(double), h->stream));
+        h->res_blocks = (int)std::min<size_t>(1024, (nn + 255) / 256);
+        HIPCHK(hipMalloc(&h->res_part, (h->res_blocks * 5 + 5) * sizeof(double)));
+    }
+    const double gy0 = -h->d.gbeta * h->p.theta_ref;
+    double* fin = h->res_part + h->res_blocks * 5;
+    if (h->esz == sizeof(double)) {
+        hipLaunchKernelGGL((residual_kernel<double>), dim3(h->res_blocks), dim3(256), 0, h->stream,
+                           fptr<double>(h, h->cur), gptr<double>(h, h->cur), h->n, h->pitch, h->plane,
+                           h->d.gbeta, gy0, h->p.force_x, h->res_ref, h->res_part);
+    } else {
+        hipLaunchKernelGGL((residual_kernel<float>), dim3(h->res_blocks), dim3(256), 0, h->stream,
+                           fptr<float>(h, h->cur), gptr<float>(h, h->cur), h->n, h->pitch, h->plane,
+                           (double)(float)h->d.gbeta, (double)(float)gy0, (double)(float)h->p.force_x,
+                           h->res_ref, h->res_part);
+    }
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(64), 0, h->stream, h->res_part,
+                       h->res_blocks, fin);
+    HIPCHK(hipGetLastError());
+    double r[5];
+    HIPCHK(hipMemcpyAsync(r, fin, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (res_theta) *res_theta = r[1] > 0 ? std::sqrt(r[0] / r[1]) : std::sqrt(r[0]);
+    if (res_u) *res_u = r[3] > 0 ? std::sqrt(r[2] / r[3]) : std::sqrt(r[2]);
+    if (r[4] > 0) return DMRT_ENONFINITE;
+    return DMRT_OK;
+}
+
+// checkpoint layout: header (8 x int64), hot wall (n doubles), f (9 n^2), g (5 n^2)
+int dmrt_state_bytes(dmrt_cavity* h, size_t* bytes)
+{
+    if (!h || !bytes) return DMRT_EINVAL;
+    const size_t nn = (size_t)h->n * h->n;
+    *bytes = 8 * sizeof(int64_t) + h->n * sizeof(double) + 14 * nn * h->esz;
+    return DMRT_OK;
+}
+
+static const int64_t kStateMagic = 0x444d5254'53544154LL;   // "DMRTSTAT"
+
+int dmrt_save_state(dmrt_cavity* h, void* host, size_t bytes)
+{
+    size_t need = 0;
+    if (!h || !host) return DMRT_EINVAL;
+    dmrt_state_bytes(h, &need);
+    if (bytes < need) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    char* out = static_cast<char*>(host);
+    int64_t hdr[8] = {kStateMagic, h->n, h->p.precision, h->step, h->p.bc_mode, 0, 0, 0};
+    std::memcpy(out, hdr, sizeof hdr);
+    std::memcpy(out + sizeof hdr, h->thw_host.data(), h->n * sizeof(double));
+    char* data = out + sizeof hdr + h->n * sizeof(double);
+    const size_t row = (size_t)h->n * h->esz;
+    char* fb = static_cast<char*>(h->fbuf) + (size_t)h->cur * 9 * h->plane * h->esz;
+    char* gb = static_cast<char*>(h->gbuf) + (size_t)h->cur * 5 * h->plane * h->esz;
+    HIPCHK(hipMemcpy2DAsync(data, row, fb, h->pitch * h->esz, row, (size_t)9 * h->n,
+                            hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpy2DAsync(data + 9 * (size_t)h->n * row, row, gb, h->pitch * h->esz, row,
+                            (size_t)5 * h->n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_load_state(dmrt_cavity* h, const void* host, size_t bytes)
+{
+    size_t need = 0;
+    if (!h || !host) return DMRT_EINVAL;
+    dmrt_state_bytes(h, &need);
+    if (bytes < need) return DMRT_EINVAL;
+    const char* in = static_cast<const char*>(host);
+    int64_t hdr[8];
+    std::memcpy(hdr, in, sizeof hdr);
+    if (hdr[0] != kStateMagic || hdr[1] != h->n || hdr[2] != h->p.precision || hdr[3] < 0)
+        return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    std::vector<double> thw(h->n);
+    std::memcpy(thw.data(), in + sizeof hdr, h->n * sizeof(double));
+    if (check_host_array(thw.data(), h->n)) return DMRT_EINVAL;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->thw_host = thw;
+    int rc = upload_hot_wall(h);
+    if (rc) return rc;
+    const char* data = in + sizeof hdr + h->n * sizeof(double);
+    const size_t row = (size_t)h->n * h->esz;
+    h->cur = 0;
+    char* fb = static_cast<char*>(h->fbuf);
+    char* gb = static_cast<char*>(h->gbuf);
+    HIPCHK(hipMemcpy2DAsync(fb, h->pitch * h->esz, data, row, row, (size_t)9 * h->n,
+                            hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpy2DAsync(gb, h->pitch * h->esz, data + 9 * (size_t)h->n * row, row, row,
+                            (size_t)5 * h->n, hipMemcpyHostToDevice, h->stream));
+    h->step = hdr[3];
+    if ((rc = reset_series(h))) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+int dmrt_set_launch(dmrt_cavity* h, int block_x, int block_y, int xcd_remap, int graph_steps)
+{
+    if (!h) return DMRT_EINVAL;
+    if (block_x != 64 && block_x != 128 && block_x != 256 && block_x != 512) return DMRT_EINVAL;
+    if (block_y < 1 || block_x * block_y > 1024) return DMRT_EINVAL;
+    if (xcd_remap != 0 && xcd_remap != 1) return DMRT_EINVAL;
+    if (graph_steps < 0) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    h->block_x = block_x;
+    h->block_y = block_y;
+    h->xcd_remap = xcd_remap;
+    h->graph_steps = graph_steps;
+    return DMRT_OK;
+}
+
+int dmrt_buffers(dmrt_cavity* h, void** f, void** g, int* current)
+{
+    if (!h) return DMRT_EINVAL;
+    if (f) *f = h->fbuf;
+    if (g) *g = h->gbuf;
+    if (current) *current = h->cur;
+    return DMRT_OK;
+}
+
+int dmrt_destroy(dmrt_cavity* h)
+{
+    if (!h) return DMRT_OK;
+    DeviceGuard g(h->dev);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->own_bufs) { (void)hipFree(h->fbuf); (void)hipFree(h->gbuf); }
+    void* ptrs[] = {h->thw_real, h->thw_dbl, h->scratch, h->nu_buf, h->res_ref, h->res_part,
+                    h->ring, h->ring_count};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return DMRT_OK;
+}
+
+const char* dmrt_strerror(int code)
+{
+    switch (code) {
+    case DMRT_OK: return "ok";
+    case DMRT_EINVAL: return "invalid argument";
+    case DMRT_EUNSTABLE: return "parameters outside the stable range of the scheme";
+    case DMRT_ENOMEM: return "out of memory";
+    case DMRT_EHIP: return "HIP runtime error";
+    case DMRT_ENONFINITE: return "non-finite values in the state";
+    case DMRT_ENODEV: return "no usable gfx950 device";
+    default: return "unknown error";
+    }
+}
+
+const char* dmrt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+"""Host-only checks of the C ABI (no GPU): the library loads, exports every
+function include/dmrt.h declares, and its host-side parameter logic agrees
+with the oracle's independent implementation."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from paper_1601_04633_amd import dmrt as D
+
+
+def test_exports_every_declared_symbol():
+    names = D.exported_symbols()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(D._lib, name), name
+    # and the binding wraps each of them under the same name
+    for name in names:
+        assert callable(getattr(D, name)), name
+
+
+def test_header_constants():
+    assert D.DMRT_OK == 0 and D.DMRT_EINVAL < 0 and D.DMRT_FP32 == 0 and D.DMRT_FP64 == 1
+    for c in (D.DMRT_EINVAL, D.DMRT_EUNSTABLE, D.DMRT_ENOMEM, D.DMRT_EHIP, D.DMRT_ENONFINITE,
+              D.DMRT_ENODEV):
+        assert D.dmrt_strerror(c) != "unknown error"
+
+
+def test_params_default():
+    p = D.dmrt_params()
+    assert D.dmrt_params_default(ctypes.byref(p)) == D.DMRT_OK
+    assert p.n == 64 and p.Ra == 1e3 and p.Pr == 0.01 and p.Ma == 0.1
+    assert p.theta_hot == 0.5 and p.theta_cold == -0.5 and math.isnan(p.gbeta_override)
+    assert D.dmrt_params_default(None) == D.DMRT_EINVAL
+
+
+@pytest.mark.parametrize("n,Ra,Pr,mode,Ma,a", [
+    (64, 1e3, 0.01, 0, 0.1, -2 / 3), (256, 1e4, 0.005, 0, 0.1, -2 / 3),
+    (1024, 1e5, 0.001, 0, 0.1, -2 / 3), (256, 1e4, 0.01, 0, 0.1, 0.25),
+    (256, 1e4, 0.01, 1, 0.009, 0.0), (32, 1e4, 0.01, 0, 0.1, -3.0)])
+def test_derive_agrees_with_oracle(oracle_mod, n, Ra, Pr, mode, Ma, a):
+    p = D.make_params(n=n, Ra=Ra, Pr=Pr, Ma=Ma, q5_mode=mode, a=a)
+    lib = D.derive(p)
+    orc = oracle_mod.derive(n, Ra, Pr, Ma, q5_mode=mode, a=a)
+    for k, v in orc.items():
+        assert math.isclose(lib[k], v, rel_tol=1e-14, abs_tol=1e-300), k
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=3), "DMRT_EINVAL"), (dict(Ma=0.0), "DMRT_EUNSTABLE"), (dict(Ra=-1.0), "DMRT_EUNSTABLE"),
+    (dict(Pr=float("nan")), "DMRT_EINVAL"), (dict(a=1.0), "DMRT_EUNSTABLE"),
+    (dict(a=-4.0), "DMRT_EUNSTABLE"), (dict(precision=7), "DMRT_EINVAL"),
+    (dict(bc_mode=9), "DMRT_EINVAL"), (dict(q5_mode=5), "DMRT_EINVAL"),
+    (dict(theta_hot=-0.5), "DMRT_EINVAL"), (dict(force_x=float("inf")), "DMRT_EINVAL"),
+    (dict(q5_mode=1), "DMRT_EUNSTABLE"),
+])
+def test_derive_errors(kw, code):
+    p = D.make_params(**kw)
+    d = D.dmrt_derived()
+    assert D.dmrt_derive(ctypes.byref(p), ctypes.byref(d)) == getattr(D, code)
+
+
+def test_derive_null():
+    assert D.dmrt_derive(None, None) == D.DMRT_EINVAL
+
+
+@pytest.mark.parametrize("n,prec,esz", [(64, "fp64", 8), (100, "fp32", 4), (1024, "fp32", 4)])
+def test_buffer_bytes(n, prec, esz):
+    p = D.make_params(n=n, precision=prec)
+    fb, gb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert D.dmrt_buffer_bytes(ctypes.byref(p), ctypes.byref(fb), ctypes.byref(gb)) == 0
+    pitch = (n + 63) // 64 * 64
+    assert fb.value == 2 * 9 * n * pitch * esz
+    assert gb.value == 2 * 5 * n * pitch * esz
+
+
+def test_null_handle_calls_are_rejected():
+    assert D.dmrt_step(None, 1) == D.DMRT_EINVAL
+    assert D.dmrt_get_fields(None, None, None, None, None) == D.DMRT_EINVAL
+    assert D.dmrt_nusselt(None, 0, None, None) == D.DMRT_EINVAL
+    assert D.dmrt_destroy(None) == D.DMRT_OK
+    out = ctypes.c_void_p()
+    p = D.make_params(n=2)
+    assert D.dmrt_create(ctypes.byref(p), None, None, None, ctypes.byref(out)) == D.DMRT_EINVAL
+    assert D.dmrt_create(None, None, None, None, ctypes.byref(out)) == D.DMRT_EINVAL

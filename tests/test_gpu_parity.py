@@ -1,0 +1,277 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bars (field-norm relative error ||x_gpu - x_ref||_2 / ||x_ref||_2 per field):
+  FP64 GPU vs oracle                 <= 1e-12 on U, V, theta, P and Nu
+  FP32 GPU vs oracle / FP64 GPU      <= 1e-5 on U, V, theta; <= 1e-4 on Nu
+Sizes span several 256-wide tiles and ragged tails (n not a multiple of 64),
+the smallest grid (n = 4), every wall configuration, and the full 1024^2
+configuration in the launch shape the benchmark times.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_1601_04633_amd import inputs
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def _pair(oracle_mod, n, Ra, Pr, precision="fp64", seed=1601, amp=1e-4, **kw):
+    from paper_1601_04633_amd.dmrt import Cavity
+    okw = {k: v for k, v in kw.items()}
+    bc = okw.pop("bc_mode", 0)
+    o = oracle_mod.Oracle(n, Ra, Pr, bc=bc, **okw)
+    c = Cavity(n=n, Ra=Ra, Pr=Pr, precision=precision, bc_mode=bc, **okw)
+    th0 = inputs.theta_noise(n, seed, amp=amp)
+    o.set_theta(th0)
+    c.set_theta(th0)
+    return o, c
+
+
+def _compare_fields(o, c, tol, names=("U", "V", "theta", "P")):
+    fo, fc = o.fields(), c.fields()
+    errs = {nm: rel(b, a) for nm, a, b in zip(("U", "V", "theta", "P"), fo, fc)}
+    bad = {k: v for k, v in errs.items() if k in names and not v <= tol}
+    assert not bad, f"field errors {errs}"
+    return errs
+
+
+@pytest.mark.parametrize("n", [4, 5, 37, 64, 100, 130, 257])
+def test_fp64_cavity_matches_oracle(oracle_mod, n):
+    print(f"[parity] fp64 cavity n={n}", flush=True)
+    o, c = _pair(oracle_mod, n, 1e4, 0.01)
+    for steps in (1, 49, 150):
+        o.step(steps)
+        c.step(steps)
+        _compare_fields(o, c, 1e-12)
+    for wall in (0, 1):
+        no, lo = o.nusselt(wall)
+        nc, lc = c.nusselt(wall)
+        assert abs(nc - no) <= 1e-12 * abs(no)
+        assert rel(lc, lo) <= 1e-12
+
+
+@pytest.mark.parametrize("bc,kw", [
+    (1, dict(gbeta_override=1e-3, force_x=2e-6)),
+    (2, dict(gbeta_override=0.0, force_x=1e-5)),
+    (3, dict(theta_ref=0.2)),
+    (0, dict(theta_ref=-0.5, a=0.3)),
+    (0, dict(q5_mode=1, Ma=0.01)),
+])
+def test_fp64_wall_modes_match_oracle(oracle_mod, bc, kw):
+    print(f"[parity] fp64 bc={bc} {kw}", flush=True)
+    o, c = _pair(oracle_mod, 70, 1e4, 0.02, amp=0.05, bc_mode=bc, **kw)
+    o.step(300)
+    c.step(300)
+    if bc == 2:
+        # x-independent forced flow without buoyancy: V and P vanish in exact
+        # arithmetic, so they are compared absolutely
+        _compare_fields(o, c, 1e-12, names=("U", "theta"))
+        for a, b in zip(o.fields()[1::2], c.fields()[1::2]):
+            assert np.abs(a).max() < 1e-17 and np.abs(b).max() < 1e-17
+    else:
+        _compare_fields(o, c, 1e-12)
+
+
+def test_fp64_hot_wall_profile_matches_oracle(oracle_mod):
+    n = 48
+    o, c = _pair(oracle_mod, n, 1e4, 0.01)
+    tw = inputs.hot_wall_profile(n, 7)
+    o.set_hot_wall(tw)
+    c.set_hot_wall(tw)
+    o.step(400)
+    c.step(400)
+    _compare_fields(o, c, 1e-12)
+    assert rel(c.nusselt(0)[1], o.nusselt(0)[1]) <= 1e-12
+
+
+def test_fp64_equilibrium_init_matches_oracle(oracle_mod):
+    """Taylor-Green-like initial velocity through dmrt_set_equilibrium."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    n = 40
+    k = 2 * np.pi / n
+    X, Y = np.meshgrid(np.arange(n), np.arange(n))
+    U = -1e-3 * np.cos(k * X) * np.sin(k * Y)
+    V = 1e-3 * np.sin(k * X) * np.cos(k * Y)
+    T = 0.1 * np.sin(k * X)
+    R = 1e-4 * np.cos(k * Y)
+    o = oracle_mod.Oracle(n, 100.0, 1.0, bc=1, gbeta_override=1e-4)
+    c = Cavity(n=n, Ra=100.0, Pr=1.0, bc_mode=1, gbeta_override=1e-4)
+    o.set_equilibrium(drho=R, U=U, V=V, theta=T)
+    c.set_equilibrium(drho=R, U=U, V=V, theta=T)
+    _compare_fields(o, c, 1e-13)
+    o.step(200)
+    c.step(200)
+    _compare_fields(o, c, 1e-12)
+
+
+def test_config0_fp64_20000_steps(oracle_mod):
+    """64^2, Ra 1e3, Pr 0.01, FP64, 20,000 steps from seeded noise: fields
+    and hot-wall Nu within 1e-12 of the oracle."""
+    print("[parity] config 64^2 fp64 20000 steps", flush=True)
+    o, c = _pair(oracle_mod, 64, 1e3, 0.01)
+    o.step(20000)
+    c.step(20000)
+    errs = _compare_fields(o, c, 1e-12)
+    no, lo = o.nusselt(0)
+    nc, lc = c.nusselt(0)
+    assert abs(nc - no) <= 1e-12 * no, (nc, no, errs)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_full_size_1024_matches_oracle(oracle_mod, precision, tol):
+    """1024^2, Ra 1e5, Pr 0.001 in the benchmark's launch shape: every field
+    after a few steps (the oracle advances 1M nodes per step slowly)."""
+    print(f"[parity] 1024^2 {precision}", flush=True)
+    o, c = _pair(oracle_mod, 1024, 1e5, 0.001, precision=precision)
+    c.set_launch(256, 1, 1, 64)
+    o.step(6)
+    c.step(6)
+    _compare_fields(o, c, tol, names=("theta",) if precision == "fp32" else ("U", "V", "theta", "P"))
+    if precision == "fp32":
+        fo, fc = o.fields(), c.fields()
+        # velocities are ~1e-6 after 6 steps: compare against the field scale
+        for a, b in zip(fo[:2], fc[:2]):
+            assert np.abs(a - b).max() <= 1e-5 * np.abs(a).max() + 1e-12
+
+
+def test_fp32_vs_fp64_steady_config0():
+    """FP32 storage as deviations from w_i rho0 vs FP64 on the GPU, steady
+    64^2 case after 20,000 steps: <= 1e-5 on U, V, theta, <= 1e-4 on Nu."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    th0 = inputs.theta_noise(64, 1601)
+    res = {}
+    for prec in ("fp32", "fp64"):
+        c = Cavity(n=64, Ra=1e3, Pr=0.01, precision=prec)
+        c.set_theta(th0)
+        c.step(20000)
+        res[prec] = (c.fields(), c.nusselt(0)[0])
+    (f32, n32), (f64, n64) = res["fp32"], res["fp64"]
+    for nm, a, b in zip(("U", "V", "theta"), f32[:3], f64[:3]):
+        assert rel(a, b) <= 1e-5, (nm, rel(a, b))
+    assert abs(n32 - n64) <= 1e-4 * n64
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_launch_shape_does_not_change_results(precision):
+    """Block shape, die-aware tile order and graph capture change only the
+    schedule: results are bitwise identical."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    n = 200
+    th0 = inputs.theta_noise(n, 3, amp=1e-2)
+    ref = None
+    for shape in [(256, 1, 1, 64), (64, 4, 0, 0), (128, 2, 1, 10), (512, 2, 0, 64), (64, 1, 1, 0)]:
+        c = Cavity(n=n, Ra=1e4, Pr=0.005, precision=precision)
+        c.set_launch(*shape)
+        c.set_theta(th0)
+        c.step(333)
+        f, g = c.raw_state()
+        if ref is None:
+            ref = (f, g)
+        else:
+            assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), shape
+
+
+def test_checkpoint_resume_is_bitwise():
+    from paper_1601_04633_amd.dmrt import Cavity
+    n = 96
+    th0 = inputs.theta_noise(n, 11)
+    a = Cavity(n=n, Ra=1e4, Pr=0.01, precision="fp32")
+    a.set_theta(th0)
+    a.step(101)
+    blob = a.save_state()
+    a.step(250)
+    b = Cavity(n=n, Ra=1e4, Pr=0.01, precision="fp32")
+    b.load_state(blob)
+    assert b.steps == 101
+    b.step(250)
+    fa, ga = a.raw_state()
+    fb, gb = b.raw_state()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+def test_nu_series_matches_direct_calls():
+    from paper_1601_04633_amd.dmrt import Cavity
+    n = 64
+    th0 = inputs.theta_noise(n, 12)
+    a = Cavity(n=n, Ra=1e4, Pr=0.01)
+    a.set_theta(th0)
+    a.nu_series(7, 1000)
+    a.set_launch(256, 1, 1, 28)
+    a.step(7 * 40 + 3)
+    series = a.nu_series_read()
+    assert len(series) == 40
+    b = Cavity(n=n, Ra=1e4, Pr=0.01)
+    b.set_theta(th0)
+    direct = []
+    for _ in range(40):
+        b.step(7)
+        direct.append(b.nusselt(0)[0])
+    np.testing.assert_array_equal(series, np.array(direct))
+
+
+def test_residual_and_watchdog():
+    from paper_1601_04633_amd.dmrt import Cavity
+    n = 32
+    c = Cavity(n=n, Ra=1e4, Pr=0.01, precision="fp32")
+    c.set_theta(inputs.theta_noise(n, 13))
+    c.residual()
+    c.step(10)
+    rt, ru, bad = c.residual()
+    assert rt > 0 and ru > 0 and not bad
+    rt2, ru2, bad = c.residual()
+    assert rt2 == 0.0 and ru2 == 0.0 and not bad
+    # plant a NaN in a checkpoint blob: the watchdog reports it
+    blob = bytearray(c.save_state())
+    off = 8 * 8 + n * 8 + 4 * 17
+    blob[off:off + 4] = np.array([np.nan], dtype=np.float32).tobytes()
+    c.load_state(bytes(blob))
+    _, _, bad = c.residual()
+    assert bad
+
+
+def test_torch_buffers_and_stream(oracle_mod):
+    import torch
+    from paper_1601_04633_amd.dmrt import Cavity
+    n = 80
+    th0 = inputs.theta_noise(n, 14)
+    a = Cavity(n=n, Ra=1e4, Pr=0.01, torch_buffers=True)
+    a.set_theta(th0)
+    a.step(120)
+    b = Cavity(n=n, Ra=1e4, Pr=0.01)
+    b.set_theta(th0)
+    b.step(120)
+    fa, ga = a.raw_state()
+    fb, gb = b.raw_state()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    f_ptr, _, _ = a.buffers()
+    assert f_ptr == a._tensors[0].data_ptr()
+
+
+def test_case1_physics_against_paper():
+    """The paper's Case 1 (Ra 1e4, Pr 0.01): steady Nu_avg 1.95, Nu_max 3.02
+    at Y = 0.30 (Section 4).  FP64 at 128^2 to Fo = 4."""
+    import json, os
+    from paper_1601_04633_amd.dmrt import Cavity
+    case = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "paper_values.json")))["cases"][0]
+    n = 128
+    c = Cavity(n=n, Ra=case["Ra"], Pr=case["Pr"])
+    c.set_theta(inputs.theta_noise(n, 1601))
+    steps = int(4 * n * n / c.derived()["alpha"])
+    c.step(steps)
+    nu, loc = c.nusselt(0)
+    nuc, _ = c.nusselt(1)
+    y = (np.arange(n) + 0.5) / n
+    print(f"[physics] case 1 n={n}: Nu {nu:.5f} cold {nuc:.5f} max {loc.max():.4f} at {y[loc.argmax()]:.4f}")
+    assert abs(nu / case["nu_avg"] - 1) < 0.01
+    assert abs(loc.max() / case["nu_max"] - 1) < 0.01
+    assert abs(y[loc.argmax()] - case["y_nu_max"]) < 0.02
+    assert abs(nuc / nu - 1) < 1e-6
