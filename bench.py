@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,xcd_remap,graph_steps")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -164,6 +166,17 @@ def main():
                      "bytes_per_node_update": WORDS_PER_NODE * esz},
         "nu_hot_wall": nu,
     }
+
+    if args.calib_copy:
+        # a plain copy of known size: 256 MiB read + 256 MiB written per launch,
+        # so HBM byte counters can be scaled against the true traffic
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes_each_way"] = src.numel() * 4
+        log("calibration copy: 5 x 256 MiB")
 
     if not args.no_extras:
         extras = {}
