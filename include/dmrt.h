@@ -214,6 +214,74 @@ int dmrt_buffers(dmrt_cavity *h, void **f, void **g, int *current);
  * for pending work.  NULL is accepted. */
 int dmrt_destroy(dmrt_cavity *h);
 
+/* ------------------------------------------------------------------------
+ * Batched sweep: many independent cavities (the paper's Ra x Pr study,
+ * Section 4 and Table 1, run as one workload).  Every member is a cavity
+ * (DMRT_BC_CAVITY) with its own n, Ra, Pr, Ma and walls; all members share
+ * one precision.  One launch per step advances every member; each member
+ * evolves bitwise as the same cavity would under dmrt_step.
+ * ------------------------------------------------------------------------ */
+typedef struct dmrt_batch dmrt_batch;   /* opaque, library-owned */
+
+/* p: array of `count` parameter sets (1 <= count <= 65535).  Members start
+ * at rest with theta = 0.  Errors: as dmrt_create for any member, EINVAL
+ * for mixed precision or a non-cavity member. */
+int dmrt_batch_create(const dmrt_params *p, int count, void *hip_stream, dmrt_batch **out);
+
+/* Re-initialise member `index` at rest with temperature theta0 (n*n host
+ * doubles of that member); the batch step counter is unchanged and a
+ * member marked dead is revived. */
+int dmrt_batch_set_theta(dmrt_batch *b, int index, const double *theta0);
+
+/* Hot-wall temperature profile of member `index` (n host doubles). */
+int dmrt_batch_set_hot_wall(dmrt_batch *b, int index, const double *theta_w);
+
+/* Schedule of the batched launch (results do not depend on it):
+ *  block_x in {64,128,256,512}, block_y >= 1, block_x*block_y <= 1024:
+ *    workgroup tile of block_x x block_y nodes of one member;
+ *  order: 0 members in the given order, 1 largest first, 2 tiles of the
+ *    members of a group interleaved round-robin;
+ *  grid_blocks: workgroups per launch, 0 = one per tile, else a persistent
+ *    grid-stride launch of that many workgroups;
+ *  group_bytes: 0 = one group; else members are packed in order into
+ *    groups of at most this much state (both copies), and
+ *  group_steps >= 1: each group advances this many steps before the next
+ *    group runs (also the number of steps per captured graph; even values
+ *    enable graph replay). */
+int dmrt_batch_set_schedule(dmrt_batch *b, int block_x, int block_y, int order, int grid_blocks,
+                            size_t group_bytes, int group_steps);
+
+/* Advance every live member nsteps >= 0 steps.  Enqueued only. */
+int dmrt_batch_step(dmrt_batch *b, long nsteps);
+int dmrt_batch_sync(dmrt_batch *b);
+int dmrt_batch_get_step(dmrt_batch *b, long *step);
+
+/* Hot-wall Nu_avg (Eqs. 18-19) of every member into nu_avg[count], reduced
+ * on the device in FP64; NaN for dead members.  Synchronises. */
+int dmrt_batch_nusselt(dmrt_batch *b, double *nu_avg);
+
+/* Per-member status into status[count]: DMRT_OK, or DMRT_ENONFINITE when
+ * the member's state holds NaN/Inf.  Such members are marked dead and
+ * skipped by later steps; the others continue.  Synchronises. */
+int dmrt_batch_status(dmrt_batch *b, int *status);
+
+/* Fields of member `index` as dmrt_get_fields.  Synchronises. */
+int dmrt_batch_get_fields(dmrt_batch *b, int index, double *U, double *V, double *theta,
+                          double *P);
+
+/* Raw post-collision distributions of member `index` at the current step:
+ * host_f gets 9*n*n, host_g 5*n*n elements of the batch precision,
+ * [population][y][x]; either may be NULL.  Synchronises. */
+int dmrt_batch_member_state(dmrt_batch *b, int index, void *host_f, void *host_g);
+
+/* Overwrite member `index`'s current distributions from host arrays laid
+ * out as dmrt_batch_member_state returns them (a per-member checkpoint
+ * restore); revives a dead member.  Synchronises. */
+int dmrt_batch_load_member_state(dmrt_batch *b, int index, const void *host_f,
+                                 const void *host_g);
+
+int dmrt_batch_destroy(dmrt_batch *b);
+
 /* Static description of an error code. */
 const char *dmrt_strerror(int code);
 

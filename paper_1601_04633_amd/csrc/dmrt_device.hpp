@@ -88,7 +88,6 @@ __device__ __forceinline__ void collide(real (&f)[9], real (&g)[5], const Coef<r
     const real a8 = (-F3 - c.s_nu * (m8 - e8)) * real(1.0 / 36.0);
 
     // f += M^T a
-    const real t38 = two * (a3 + a8);           // shared by the four axis links
     const real d2 = two * a3 + a8;              // shared by the four diagonals
     f[0] += real(4) * (a8 - a3);
     f[1] += a1 - a3 + a4 - two * a6 - two * a8;
@@ -99,7 +98,6 @@ __device__ __forceinline__ void collide(real (&f)[9], real (&g)[5], const Coef<r
     f[6] += d2 + (a2 - a1) + (a7 - a5 - a6);
     f[7] += d2 - (a1 + a2) + (a5 - a6 - a7);
     f[8] += d2 + (a1 - a2) + (a6 - a5 - a7);
-    (void)t38;
 
     // D2Q5, Eqs. 36-42 (last row of N read as e_x^2 - e_y^2)
     const real n1 = g[1] - g[3];
@@ -149,23 +147,18 @@ __device__ __forceinline__ int tile_of_block(int bid, int nblocks, int remap)
     return (bid & 7) * per + (bid >> 3);
 }
 
+// One node update (rows a1-a5): gather from the current copy with the wall
+// rules, collide in registers, store into the other copy.
 template <typename real, int BC>
-__global__ void __launch_bounds__(1024) step_kernel(StepArgs<real> A)
+__device__ __forceinline__ void node_update(const real* __restrict__ fi, const real* __restrict__ gi,
+                                            real* __restrict__ fo, real* __restrict__ go,
+                                            const real* __restrict__ thw, int n, int pitch, int P,
+                                            int x, int y, const Coef<real>& c)
 {
-    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
-    if (tile >= A.tiles) return;
-    const int ty = tile / A.tiles_x;
-    const int tx = tile - ty * A.tiles_x;
-    const int x = tx * blockDim.x + threadIdx.x;
-    const int y = ty * blockDim.y + threadIdx.y;
-    const int n = A.n;
-    if (x >= n || y >= n) return;
-
     constexpr bool PX = (BC == BC_PERIODIC || BC == BC_CHANNEL_X);
     constexpr bool PY = (BC == BC_PERIODIC);
     constexpr bool ABB = (BC == BC_CAVITY);
 
-    const int pitch = A.pitch, P = A.plane;
     const int k = y * pitch + x;
     // neighbour offsets (wrapped in periodic directions)
     const bool hxm = PX || x > 0, hxp = PX || x < n - 1;
@@ -175,8 +168,6 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<real> A)
     const int dym = (PY && y == 0) ? (n - 1) * pitch : -pitch;
     const int dyp = (PY && y == n - 1) ? -(n - 1) * pitch : pitch;
 
-    const real* __restrict__ fi = A.fin;
-    const real* __restrict__ gi = A.gin;
     real f[9], g[5];
     // pull: f_i(r) = f*_i(r - e_i), else bounce-back f*_opp(i)(r)
     f[0] = fi[k];
@@ -193,22 +184,74 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<real> A)
     g[2] = hym ? gi[2 * P + k + dym] : gi[4 * P + k];       // Eq. 44
     g[4] = hyp ? gi[4 * P + k + dyp] : gi[2 * P + k];
     if (ABB) {                                              // Eq. 45
-        g[1] = hxm ? gi[1 * P + k + dxm] : A.c.cabb * A.thw[y] - gi[3 * P + k];
-        g[3] = hxp ? gi[3 * P + k + dxp] : A.c.cold - gi[1 * P + k];
+        g[1] = hxm ? gi[1 * P + k + dxm] : c.cabb * thw[y] - gi[3 * P + k];
+        g[3] = hxp ? gi[3 * P + k + dxp] : c.cold - gi[1 * P + k];
     } else {
         g[1] = hxm ? gi[1 * P + k + dxm] : gi[3 * P + k];
         g[3] = hxp ? gi[3 * P + k + dxp] : gi[1 * P + k];
     }
 
     real th, ux, uy;
-    collide<real>(f, g, A.c, th, ux, uy);
+    collide<real>(f, g, c, th, ux, uy);
 
-    real* __restrict__ fo = A.fout;
-    real* __restrict__ go = A.gout;
 #pragma unroll
     for (int i = 0; i < 9; ++i) fo[i * P + k] = f[i];
 #pragma unroll
     for (int i = 0; i < 5; ++i) go[i * P + k] = g[i];
+}
+
+template <typename real, int BC>
+__global__ void __launch_bounds__(1024) step_kernel(StepArgs<real> A)
+{
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;
+    const int ty = tile / A.tiles_x;
+    const int tx = tile - ty * A.tiles_x;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y = ty * blockDim.y + threadIdx.y;
+    if (x >= A.n || y >= A.n) return;
+    node_update<real, BC>(A.fin, A.gin, A.fout, A.gout, A.thw, A.n, A.pitch, A.plane, x, y, A.c);
+}
+
+// ---------------------------------------------------------------------------
+// Batched sweep: many independent cavities advanced by one launch
+// ---------------------------------------------------------------------------
+// Per-cavity parameter block, resident in device memory.
+template <typename real>
+struct CavityDev {
+    real* f[2];            // ping-pong copies of the 9 D2Q9 planes
+    real* g[2];            // ping-pong copies of the 5 D2Q5 planes
+    const real* thw;       // hot-wall theta per row
+    const double* thw_d;   // the same in FP64 (Nusselt number)
+    double H, inv_dT, theta_cold;
+    int n, pitch, plane;
+    int dead;              // 1: skipped (non-finite state was detected)
+    Coef<real> c;
+};
+
+// One entry per workgroup-sized tile: cavity and tile origin.
+struct TileRef {
+    int cav, x0, y0, pad;
+};
+
+// Grid-stride over the tiles [t_begin, t_end): with gridDim.x equal to the
+// tile count every workgroup takes one tile; with fewer workgroups the
+// launch is persistent.  All cavities step from copy `cur` to `cur ^ 1`.
+template <typename real>
+__global__ void __launch_bounds__(1024) batch_step_kernel(const CavityDev<real>* __restrict__ cavs,
+                                                          const TileRef* __restrict__ tiles,
+                                                          int t_begin, int t_end, int cur)
+{
+    for (int t = t_begin + blockIdx.x; t < t_end; t += gridDim.x) {
+        const TileRef tr = tiles[t];
+        const CavityDev<real>& cv = cavs[tr.cav];
+        if (cv.dead) continue;
+        const int x = tr.x0 + threadIdx.x;
+        const int y = tr.y0 + threadIdx.y;
+        if (x >= cv.n || y >= cv.n) continue;
+        node_update<real, BC_CAVITY>(cv.f[cur], cv.g[cur], cv.f[cur ^ 1], cv.g[cur ^ 1], cv.thw,
+                                     cv.n, cv.pitch, cv.plane, x, y, cv.c);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -293,12 +336,13 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Sum over the rows of the local Nusselt numbers of one wall, by one
+// workgroup of 256 threads; returns the average to thread 0.
 template <typename real>
-__global__ void __launch_bounds__(256) nusselt_kernel(
-    const real* __restrict__ gs, int n, int pitch, int plane, int wall,
-    const double* __restrict__ thw, double theta_cold, double H, double inv_dT,
-    double* __restrict__ nu_local, double* __restrict__ nu_avg,
-    double* __restrict__ ring, unsigned long long* __restrict__ ring_count, long ring_cap)
+__device__ __forceinline__ double nusselt_block(const real* __restrict__ gs, int n, int pitch,
+                                                int plane, int wall, const double* __restrict__ thw,
+                                                double theta_cold, double H, double inv_dT,
+                                                double* __restrict__ nu_local)
 {
     __shared__ double part[4];
     double acc = 0.0;
@@ -323,10 +367,22 @@ __global__ void __launch_bounds__(256) nusselt_kernel(
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) part[wid] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
+    double s = 0.0;
+    if (threadIdx.x == 0)
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
-        const double avg = s / n;
+    return s / n;
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) nusselt_kernel(
+    const real* __restrict__ gs, int n, int pitch, int plane, int wall,
+    const double* __restrict__ thw, double theta_cold, double H, double inv_dT,
+    double* __restrict__ nu_local, double* __restrict__ nu_avg,
+    double* __restrict__ ring, unsigned long long* __restrict__ ring_count, long ring_cap)
+{
+    const double avg = nusselt_block<real>(gs, n, pitch, plane, wall, thw, theta_cold, H, inv_dT,
+                                           nu_local);
+    if (threadIdx.x == 0) {
         if (nu_avg) *nu_avg = avg;
         if (ring) {
             const unsigned long long c = *ring_count;
@@ -334,6 +390,40 @@ __global__ void __launch_bounds__(256) nusselt_kernel(
             *ring_count = c + 1;
         }
     }
+}
+
+// Hot-wall Nusselt number of every cavity of a batch: one workgroup each.
+template <typename real>
+__global__ void __launch_bounds__(256) batch_nusselt_kernel(const CavityDev<real>* __restrict__ cavs,
+                                                            int cur, double* __restrict__ out)
+{
+    const CavityDev<real>& cv = cavs[blockIdx.x];
+    const double avg = nusselt_block<real>(cv.g[cur], cv.n, cv.pitch, cv.plane, 0, cv.thw_d,
+                                           cv.theta_cold, cv.H, cv.inv_dT, nullptr);
+    if (threadIdx.x == 0) out[blockIdx.x] = cv.dead ? __builtin_nan("") : avg;
+}
+
+// Non-finite check of every cavity's state: grid (blocks per cavity, count).
+template <typename real>
+__global__ void __launch_bounds__(256) batch_check_kernel(const CavityDev<real>* __restrict__ cavs,
+                                                          int cur, int* __restrict__ flags)
+{
+    const CavityDev<real>& cv = cavs[blockIdx.y];
+    const long nn = (long)cv.n * cv.n;
+    int bad = 0;
+    for (long o = (long)blockIdx.x * blockDim.x + threadIdx.x; o < nn;
+         o += (long)gridDim.x * blockDim.x) {
+        const int y = (int)(o / cv.n), x = (int)(o - (long)y * cv.n);
+        const int k = y * cv.pitch + x;
+        real s = real(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) s += fabs(cv.f[cur][i * cv.plane + k]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) s += fabs(cv.g[cur][i * cv.plane + k]);
+        bad |= !isfinite(s);
+    }
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0 && bad) atomicOr(&flags[blockIdx.y], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,7 +469,7 @@ __global__ void __launch_bounds__(256) residual_kernel(
     }
 }
 
-__global__ void __launch_bounds__(64) residual_final_kernel(const double* __restrict__ part,
+static __global__ void __launch_bounds__(64) residual_final_kernel(const double* __restrict__ part,
                                                             int nparts, double* __restrict__ out)
 {
     if (threadIdx.x < 5) {

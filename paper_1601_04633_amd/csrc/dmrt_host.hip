@@ -27,6 +27,8 @@ thread_local std::string g_last_error;
 
 namespace dmrt {
 
+void set_last_error(const char* msg) { g_last_error = msg; }
+
 int record_hip(hipError_t e, const char* what)
 {
     if (e == hipSuccess) return DMRT_OK;
@@ -98,11 +100,7 @@ int pitch_of(int n) { return (n + 63) / 64 * 64; }
 
 using namespace dmrt;
 
-#define HIPCHK(expr)                                        \
-    do {                                                    \
-        hipError_t e_ = (expr);                             \
-        if (e_ != hipSuccess) return record_hip(e_, #expr); \
-    } while (0)
+#define HIPCHK(expr) DMRT_HIPCHK(expr)
 
 namespace {
 
@@ -120,23 +118,6 @@ struct DeviceGuard {
         if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
     }
 };
-
-size_t elem_size(int precision) { return precision == DMRT_FP64 ? sizeof(double) : sizeof(float); }
-
-template <typename real>
-Coef<real> make_coef(const dmrt_params& p, const dmrt_derived& d)
-{
-    Coef<real> c;
-    c.s_nu = real(d.s_nu); c.s_q = real(d.s_q);
-    c.sk = real(d.sigma_k); c.se = real(d.sigma_e); c.sn = real(d.sigma_nu);
-    c.a = real(d.a);
-    c.cabb = real((4.0 + d.a) / 10.0);
-    c.gbeta = real(d.gbeta);
-    c.gy0 = real(-d.gbeta * p.theta_ref);
-    c.gx = real(p.force_x);
-    c.cold = real((4.0 + d.a) / 10.0 * p.theta_cold);
-    return c;
-}
 
 }  // namespace
 

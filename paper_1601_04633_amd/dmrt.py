@@ -95,6 +95,19 @@ _SIGS = {
     "dmrt_set_launch": [_vp, _c_int, _c_int, _c_int, _c_int],
     "dmrt_buffers": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_c_int)],
     "dmrt_destroy": [_vp],
+    "dmrt_batch_create": [_P, _c_int, _vp, ctypes.POINTER(_vp)],
+    "dmrt_batch_set_theta": [_vp, _c_int, _dp],
+    "dmrt_batch_set_hot_wall": [_vp, _c_int, _dp],
+    "dmrt_batch_set_schedule": [_vp, _c_int, _c_int, _c_int, _c_int, _c_size, _c_int],
+    "dmrt_batch_step": [_vp, _c_long],
+    "dmrt_batch_sync": [_vp],
+    "dmrt_batch_get_step": [_vp, ctypes.POINTER(_c_long)],
+    "dmrt_batch_nusselt": [_vp, _dp],
+    "dmrt_batch_status": [_vp, ctypes.POINTER(_c_int)],
+    "dmrt_batch_get_fields": [_vp, _c_int, _dp, _dp, _dp, _dp],
+    "dmrt_batch_member_state": [_vp, _c_int, _vp, _vp],
+    "dmrt_batch_load_member_state": [_vp, _c_int, _vp, _vp],
+    "dmrt_batch_destroy": [_vp],
 }
 
 for _name, _args in _SIGS.items():
@@ -304,3 +317,96 @@ class Cavity:
         off = 8 * 8 + n * 8
         data = np.frombuffer(blob, dtype=dt, offset=off, count=14 * n * n)
         return data[:9 * n * n].reshape(9, n, n).copy(), data[9 * n * n:].reshape(5, n, n).copy()
+
+
+class Batch:
+    """A batched sweep of independent cavities (one launch per step).
+
+    ``members``: list of dicts of ``make_params`` keywords (n, Ra, Pr, ...),
+    all with the same precision."""
+
+    def __init__(self, members, precision="fp32", stream=None):
+        self.members = [dict(m) for m in members]
+        arr = (dmrt_params * len(members))()
+        for i, m in enumerate(self.members):
+            kw = dict(m)
+            kw.setdefault("precision", precision)
+            arr[i] = make_params(**kw)
+        self.params = arr
+        self.count = len(members)
+        self.precision = arr[0].precision
+        h = ctypes.c_void_p()
+        check(dmrt_batch_create(arr, self.count, stream, ctypes.byref(h)), "dmrt_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            dmrt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def n(self, i):
+        return self.params[i].n
+
+    def set_theta(self, i, theta0):
+        check(dmrt_batch_set_theta(self._h, i, _ptr(_arr(theta0, self.n(i) ** 2))),
+              "dmrt_batch_set_theta")
+
+    def set_hot_wall(self, i, theta_w):
+        check(dmrt_batch_set_hot_wall(self._h, i, _ptr(_arr(theta_w, self.n(i)))),
+              "dmrt_batch_set_hot_wall")
+
+    def set_schedule(self, block_x=64, block_y=4, order=1, grid_blocks=0, group_bytes=0,
+                     group_steps=64):
+        check(dmrt_batch_set_schedule(self._h, block_x, block_y, order, grid_blocks,
+                                      int(group_bytes), group_steps), "dmrt_batch_set_schedule")
+
+    def step(self, nsteps=1):
+        check(dmrt_batch_step(self._h, int(nsteps)), "dmrt_batch_step")
+
+    def sync(self):
+        check(dmrt_batch_sync(self._h), "dmrt_batch_sync")
+
+    @property
+    def steps(self):
+        s = ctypes.c_long(0)
+        check(dmrt_batch_get_step(self._h, ctypes.byref(s)), "dmrt_batch_get_step")
+        return s.value
+
+    def nusselt(self):
+        out = np.empty(self.count)
+        check(dmrt_batch_nusselt(self._h, _ptr(out)), "dmrt_batch_nusselt")
+        return out
+
+    def status(self):
+        out = (ctypes.c_int * self.count)()
+        check(dmrt_batch_status(self._h, out), "dmrt_batch_status")
+        return np.array(list(out))
+
+    def fields(self, i):
+        n = self.n(i)
+        out = [np.empty(n * n) for _ in range(4)]
+        check(dmrt_batch_get_fields(self._h, i, *[_ptr(a) for a in out]), "dmrt_batch_get_fields")
+        return tuple(a.reshape(n, n) for a in out)
+
+    def raw_state(self, i):
+        n = self.n(i)
+        dt = np.float64 if self.precision == DMRT_FP64 else np.float32
+        f = np.empty((9, n, n), dtype=dt)
+        g = np.empty((5, n, n), dtype=dt)
+        check(dmrt_batch_member_state(self._h, i, f.ctypes.data, g.ctypes.data),
+              "dmrt_batch_member_state")
+        return f, g
+
+    def load_state(self, i, f, g):
+        dt = np.float64 if self.precision == DMRT_FP64 else np.float32
+        n = self.n(i)
+        f = np.ascontiguousarray(f, dtype=dt).reshape(9, n, n)
+        g = np.ascontiguousarray(g, dtype=dt).reshape(5, n, n)
+        check(dmrt_batch_load_member_state(self._h, i, f.ctypes.data, g.ctypes.data),
+              "dmrt_batch_load_member_state")
