@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -86,6 +88,72 @@ def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601):
     return ms, mlups, ms / steps, nu
 
 
+def bench_batch(steps, single_steps, count=64, seed=4633, tune=True):
+    """The Ra x Pr sweep (count cavities, sides {64..512}, FP32) in one launch
+    per step, against the same cavities stepped one by one with the
+    single-cavity kernel (graphs and tuned launch shapes in both)."""
+    import torch
+    from paper_1601_04633_amd import autotune, inputs
+    from paper_1601_04633_amd.dmrt import Batch, Cavity
+    specs = inputs.batch_cavities(count, seed)
+    members = [dict(n=s, Ra=ra, Pr=pr) for s, ra, pr in specs]
+    nodes = sum(m["n"] ** 2 for m in members)
+    stream = torch.cuda.Stream()
+    b = Batch(members, precision="fp32", stream=stream.cuda_stream)
+    for i, m in enumerate(members):
+        b.set_theta(i, inputs.theta_noise(m["n"], seed + i))
+    cfg = None
+    if tune:
+        cfg, _, trials = autotune.tune_batch(b, stream_ptr=stream.cuda_stream, use_cache=False)
+        log(f"batch: tuned schedule {cfg} after {len(trials)} trials")
+    g = cfg["group"][1] if cfg else 64
+    steps = max(steps // g, 1) * g
+    b.step(2 * g)
+    b.sync()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    b.step(steps)
+    t1.record(stream)
+    t1.synchronize()
+    sec = t0.elapsed_time(t1) * 1e-3
+    nu = b.nusselt()
+    status = b.status()
+    b.close()
+    batch_mlups = nodes * steps / sec / 1e6
+
+    # one by one: every member alone for single_steps steps
+    total = 0.0
+    tuned = {}
+    for i, m in enumerate(members):
+        c = Cavity(precision="fp32", stream=stream.cuda_stream, **m)
+        c.set_theta(inputs.theta_noise(m["n"], seed + i))
+        if m["n"] not in tuned:
+            tuned[m["n"]] = autotune.tune_cavity(c, stream_ptr=stream.cuda_stream, use_cache=False)[0]
+        else:
+            best = tuned[m["n"]]
+            c.set_launch(best["block"][0], best["block"][1], best["xcd_remap"], 64)
+        c.step(128)
+        c.sync()
+        t0.record(stream)
+        c.step(single_steps)
+        t1.record(stream)
+        t1.synchronize()
+        total += t0.elapsed_time(t1) * 1e-3
+        c.close()
+    single_mlups = nodes * single_steps / total / 1e6
+    return {"cavities": count, "nodes": nodes, "precision": "fp32",
+            "batch_steps_timed": steps, "single_steps_timed_each": single_steps,
+            "batch_mlups": round(batch_mlups, 1), "one_by_one_mlups": round(single_mlups, 1),
+            "batch_over_one_by_one": round(batch_mlups / single_mlups, 3),
+            "batch_hbm_frac": round(batch_mlups * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4),
+            "schedule": {k: list(v) if isinstance(v, tuple) else v for k, v in cfg.items()} if cfg else None,
+            "single_launch_by_side": {str(k): {"block": list(v["block"]), "xcd_remap": v["xcd_remap"]}
+                                      for k, v in tuned.items()},
+            "dead_members": int((status != 0).sum()),
+            "nu_hot_wall_mean": float(nu[np.isfinite(nu)].mean())}
+
+
 def cpu_baseline(n, Ra, Pr, budget_s=15.0):
     """The FP64 oracle on the host (single thread) over a bounded sample of
     the same workload: whole steps of the same cavity until ~budget_s."""
@@ -118,6 +186,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,xcd_remap,graph_steps")
+    ap.add_argument("--batch-steps", type=int, default=5000)
+    ap.add_argument("--single-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -189,6 +259,10 @@ def main():
         extras["fp32_2048_mlups"] = round(m2k, 1)
         extras["fp32_2048_hbm_frac"] = round(112 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         out["extras"] = extras
+        log("batch: 64-cavity Ra x Pr sweep vs one by one")
+        out["batch"] = bench_batch(args.batch_steps, args.single_steps)
+        log(f"batch: {out['batch']['batch_mlups']} MLUPS vs one by one "
+            f"{out['batch']['one_by_one_mlups']} MLUPS")
 
     if not args.no_cpu:
         log("cpu baseline (oracle, single thread)")

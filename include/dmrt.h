@@ -215,6 +215,38 @@ int dmrt_buffers(dmrt_cavity *h, void **f, void **g, int *current);
 int dmrt_destroy(dmrt_cavity *h);
 
 /* ------------------------------------------------------------------------
+ * Gradient of the time-averaged hot-wall Nusselt number (reverse mode).
+ * Objective: J = mean of Nu_avg (Eqs. 18-19, hot wall) over the last
+ * avg_last of nsteps steps, started from the rest state with the
+ * temperature field theta0 of the last dmrt_set_theta (set_equilibrium with
+ * only theta also qualifies).  Gradients with respect to the hot-wall
+ * profile theta_w(y) (Eq. 45 and Eq. 18) and theta0.  Only DMRT_BC_CAVITY.
+ * The forward stores a checkpoint every ckpt_every steps; the backward
+ * recomputes each segment from its checkpoint and runs the hand-written
+ * adjoint step kernel.  Device memory: (ceil(nsteps/ckpt_every) +
+ * ckpt_every + 2) states of 14 n^2 elements, held until
+ * dmrt_adjoint_release or dmrt_destroy.
+ * ------------------------------------------------------------------------ */
+
+/* Forward run: re-initialises from theta0, advances nsteps (the handle ends
+ * at step nsteps) and returns J (FP64).  EINVAL if no rest-state theta0 was
+ * set, if 1 <= avg_last <= nsteps or ckpt_every >= 1 fails, or for a
+ * non-cavity handle.  Synchronises. */
+int dmrt_adjoint_forward(dmrt_cavity *h, long nsteps, long avg_last, long ckpt_every, double *J);
+
+/* Backward run after dmrt_adjoint_forward: dJ_dthetaw (n doubles) and
+ * dJ_dtheta0 (n*n doubles, y-major), either may be NULL.  The parameter
+ * gradient is accumulated in FP64 on the device.  Synchronises. */
+int dmrt_adjoint_backward(dmrt_cavity *h, double *dJ_dthetaw, double *dJ_dtheta0);
+
+/* dmrt_adjoint_forward followed by dmrt_adjoint_backward. */
+int dmrt_adjoint_nu(dmrt_cavity *h, long nsteps, long avg_last, long ckpt_every, double *J,
+                    double *dJ_dthetaw, double *dJ_dtheta0);
+
+/* Free the checkpoint, segment and adjoint buffers. */
+int dmrt_adjoint_release(dmrt_cavity *h);
+
+/* ------------------------------------------------------------------------
  * Batched sweep: many independent cavities (the paper's Ra x Pr study,
  * Section 4 and Table 1, run as one workload).  Every member is a cavity
  * (DMRT_BC_CAVITY) with its own n, Ra, Pr, Ma and walls; all members share

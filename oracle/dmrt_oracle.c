@@ -538,3 +538,21 @@ int orc_nusselt(const orc_t *s, int wall, double *nu_avg, double *nu_local)
     if (nu_avg) *nu_avg = sum / n;
     return ORC_OK;
 }
+
+/* Objective of the gradient problem: J = mean of the hot-wall Nu_avg
+ * (Eqs. 18-19) over the last K of N steps taken from the current state. */
+int orc_objective(orc_t *s, long N, long K, double *J)
+{
+    if (!s || N < 1 || K < 1 || K > N || !J) return ORC_EINVAL;
+    double acc = 0.0;
+    for (long m = 1; m <= N; ++m) {
+        step_once(s);
+        if (m > N - K) {
+            double nu;
+            orc_nusselt(s, 0, &nu, NULL);
+            acc += nu;
+        }
+    }
+    *J = acc / K;
+    return ORC_OK;
+}

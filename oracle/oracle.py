@@ -82,6 +82,8 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
+        L.orc_objective.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_long, _dp]
+        L.orc_objective.restype = ctypes.c_int
         L.orc_steps.argtypes = [ctypes.c_void_p]
         L.orc_steps.restype = ctypes.c_long
         _lib = L
@@ -200,6 +202,13 @@ class Oracle:
     @property
     def steps(self):
         return lib().orc_steps(self._h)
+
+    def objective(self, nsteps, avg_last):
+        """Step nsteps and return the mean hot-wall Nu_avg over the last
+        avg_last steps."""
+        J = ctypes.c_double(0.0)
+        _check(lib().orc_objective(self._h, int(nsteps), int(avg_last), ctypes.byref(J)))
+        return J.value
 
     # -- diagnostics ----------------------------------------------------------
     def fields(self):

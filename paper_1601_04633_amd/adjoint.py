@@ -1,0 +1,40 @@
+"""torch.autograd.Function around the library's hand-written adjoint.
+
+``NuObjective.apply(theta_w, theta0, cavity, nsteps, avg_last, ckpt_every)``
+returns J, the mean hot-wall Nusselt number (Eqs. 18-19) over the last
+``avg_last`` of ``nsteps`` steps of ``cavity`` started at rest with the
+temperature field ``theta0`` and hot-wall profile ``theta_w``.  Its backward
+is dmrt_adjoint_backward: recompute from checkpoints plus the adjoint step
+kernel on the GPU; the tensors are host float64 (they cross the C ABI as
+host arrays).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+
+class NuObjective(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta_w, theta0, cavity, nsteps, avg_last, ckpt_every=500):
+        tw = theta_w.detach().to("cpu", torch.float64).numpy()
+        t0 = theta0.detach().to("cpu", torch.float64).numpy()
+        cavity.set_hot_wall(tw)
+        cavity.set_theta(t0)
+        J = cavity.adjoint_forward(nsteps, avg_last, ckpt_every)
+        ctx.cavity = cavity
+        ctx.shapes = (theta_w.shape, theta0.shape)
+        ctx.devices = (theta_w.device, theta0.device)
+        return torch.tensor(J, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        gw, g0 = ctx.cavity.adjoint_backward()
+        s = float(grad_out)
+        gw_t = torch.from_numpy(np.ascontiguousarray(gw * s)).reshape(ctx.shapes[0]).to(ctx.devices[0])
+        g0_t = torch.from_numpy(np.ascontiguousarray(g0 * s)).reshape(ctx.shapes[1]).to(ctx.devices[1])
+        return gw_t, g0_t, None, None, None, None
+
+
+def nu_objective(theta_w, theta0, cavity, nsteps, avg_last, ckpt_every=500):
+    return NuObjective.apply(theta_w, theta0, cavity, nsteps, avg_last, ckpt_every)

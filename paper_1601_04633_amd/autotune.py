@@ -1,0 +1,194 @@
+"""Autotuner for the launch shapes of libdmrt.
+
+Results never depend on the launch shape (the kernels are bitwise
+insensitive to it); only the time does.  The tuner times short runs of the
+actual workload and keeps the fastest setting, searching one dimension at a
+time from a default (coordinate descent, two sweeps).  Winners are cached
+in a JSON file keyed by (device architecture, precision, member sizes).
+
+Batch schedule dimensions (dmrt_batch_set_schedule): tile shape, tile
+order, workgroups per launch, and cavity groups sized for the 256 MB
+last-level cache that run several steps before the next group.
+Single-cavity dimensions (dmrt_set_launch): tile shape and die-aware tile
+order.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+CACHE_PATH = os.environ.get("DMRT_AUTOTUNE_CACHE",
+                            os.path.join(os.path.expanduser("~"), ".cache", "dmrt_autotune.json"))
+
+MB = 1 << 20
+
+BATCH_SPACE = {
+    "block": [(64, 4), (64, 2), (64, 8), (128, 2), (128, 4), (256, 1), (64, 1)],
+    "order": [1, 0, 2],
+    "grid_blocks": [0, 4096, 16384],
+    "group": [(0, 64), (96 * MB, 8), (96 * MB, 32), (160 * MB, 16), (160 * MB, 64),
+              (224 * MB, 32)],
+}
+BATCH_DEFAULT = {"block": (64, 4), "order": 1, "grid_blocks": 0, "group": (0, 64)}
+
+CAVITY_SPACE = {
+    "block": [(256, 1), (128, 2), (64, 4), (512, 1), (128, 1), (64, 1), (256, 2)],
+    "xcd_remap": [1, 0],
+}
+CAVITY_DEFAULT = {"block": (256, 1), "xcd_remap": 1}
+
+
+def _arch():
+    try:
+        import torch
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def _load_cache():
+    try:
+        with open(CACHE_PATH) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(key, value):
+    cache = _load_cache()
+    cache[key] = value
+    try:
+        os.makedirs(os.path.dirname(CACHE_PATH), exist_ok=True)
+        tmp = CACHE_PATH + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, CACHE_PATH)
+    except OSError:
+        pass
+
+
+def _timer(stream_ptr):
+    """Returns (start, stop) closures timing work on the handle's stream."""
+    try:
+        import torch
+        ext = torch.cuda.ExternalStream(stream_ptr) if stream_ptr else None
+    except Exception:
+        ext = None
+    if ext is not None:
+        import torch
+        ev = [torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+
+        def start():
+            ev[0].record(ext)
+
+        def stop():
+            ev[1].record(ext)
+            ev[1].synchronize()
+            return ev[0].elapsed_time(ev[1]) * 1e-3
+        return start, stop
+    t = [0.0]
+
+    def start():
+        t[0] = time.perf_counter()
+
+    def stop():
+        return time.perf_counter() - t[0]
+    return start, stop
+
+
+def _coordinate_search(space, default, measure, sweeps=2):
+    best = dict(default)
+    best_t = measure(best)
+    trials = [(dict(best), best_t)]
+    for _ in range(sweeps):
+        improved = False
+        for dim, values in space.items():
+            for v in values:
+                if v == best[dim]:
+                    continue
+                cand = dict(best)
+                cand[dim] = v
+                t = measure(cand)
+                trials.append((dict(cand), t))
+                if t < best_t:
+                    best, best_t, improved = cand, t, True
+        if not improved:
+            break
+    return best, best_t, trials
+
+
+def batch_key(batch):
+    sizes = sorted(batch.n(i) for i in range(batch.count))
+    h = hashlib.sha1(json.dumps(sizes).encode()).hexdigest()[:12]
+    return f"batch|{_arch()}|{'fp64' if batch.precision == 1 else 'fp32'}|{len(sizes)}|{h}"
+
+
+def apply_batch(batch, cfg):
+    bx, by = cfg["block"]
+    gb, gs = cfg["group"]
+    batch.set_schedule(block_x=bx, block_y=by, order=cfg["order"],
+                       grid_blocks=cfg["grid_blocks"], group_bytes=gb, group_steps=gs)
+
+
+def tune_batch(batch, stream_ptr=None, min_steps=128, use_cache=True, verbose=False):
+    """Pick the fastest schedule for this batch; leaves it applied.
+    Returns (config, seconds per step, trials)."""
+    key = batch_key(batch)
+    if use_cache:
+        hit = _load_cache().get(key)
+        if hit:
+            cfg = {"block": tuple(hit["block"]), "order": hit["order"],
+                   "grid_blocks": hit["grid_blocks"], "group": tuple(hit["group"])}
+            apply_batch(batch, cfg)
+            return cfg, hit.get("sec_per_step"), []
+    start, stop = _timer(stream_ptr)
+
+    def measure(cfg):
+        apply_batch(batch, cfg)
+        g = cfg["group"][1]
+        steps = max(min_steps, g) // g * g
+        batch.step(2 * g)           # builds the captured graph
+        batch.sync()
+        start()
+        batch.step(steps)
+        t = stop() / steps
+        if verbose:
+            print(f"[autotune] batch {cfg} {t * 1e6:.1f} us/step", flush=True)
+        return t
+
+    best, best_t, trials = _coordinate_search(BATCH_SPACE, BATCH_DEFAULT, measure)
+    apply_batch(batch, best)
+    _store_cache(key, {"block": list(best["block"]), "order": best["order"],
+                       "grid_blocks": best["grid_blocks"], "group": list(best["group"]),
+                       "sec_per_step": best_t})
+    return best, best_t, trials
+
+
+def tune_cavity(cavity, stream_ptr=None, steps=256, use_cache=True, verbose=False):
+    """Pick the fastest single-cavity launch shape; leaves it applied."""
+    key = f"cavity|{_arch()}|{'fp64' if cavity.params.precision == 1 else 'fp32'}|{cavity.n}"
+    if use_cache:
+        hit = _load_cache().get(key)
+        if hit:
+            cavity.set_launch(hit["block"][0], hit["block"][1], hit["xcd_remap"], 64)
+            return hit, hit.get("sec_per_step"), []
+    start, stop = _timer(stream_ptr)
+
+    def measure(cfg):
+        cavity.set_launch(cfg["block"][0], cfg["block"][1], cfg["xcd_remap"], 64)
+        cavity.step(128)
+        cavity.sync()
+        start()
+        cavity.step(steps)
+        t = stop() / steps
+        if verbose:
+            print(f"[autotune] cavity n={cavity.n} {cfg} {t * 1e6:.2f} us/step", flush=True)
+        return t
+
+    best, best_t, trials = _coordinate_search(CAVITY_SPACE, CAVITY_DEFAULT, measure, sweeps=1)
+    cavity.set_launch(best["block"][0], best["block"][1], best["xcd_remap"], 64)
+    _store_cache(key, {"block": list(best["block"]), "xcd_remap": best["xcd_remap"],
+                       "sec_per_step": best_t})
+    return best, best_t, trials

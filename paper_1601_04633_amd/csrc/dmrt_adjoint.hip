@@ -1,0 +1,367 @@
+// dmrt_adjoint.hip -- reverse-mode derivative of the time-averaged hot-wall
+// Nusselt number (Eqs. 18-19) of a cavity run with respect to the hot-wall
+// temperature profile (Eq. 45) and the initial temperature field, by
+// checkpoint-and-recompute.
+//
+// Forward: from the rest state with theta0 (the last dmrt_set_theta), N
+// steps; the state is copied to a checkpoint every C steps, and on the last
+// K steps a variant of the step kernel accumulates each row's Nusselt sum in
+// FP64.  J = H / (3 dT n K) * sum over rows and window steps.
+// Backward: for each segment of C steps, newest first, the states of the
+// segment are recomputed from its checkpoint into a segment buffer, then
+// the adjoint step kernel runs from the segment's last step to its first
+// (lambda ping-pong).  A captured graph of one full segment is replayed for
+// every full segment; the segment's first step index is read from device
+// memory, which is updated before each replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dmrt.h"
+#include "dmrt_device.hpp"
+#include "dmrt_internal.hpp"
+
+using namespace dmrt;
+
+#define HIPCHK(expr) DMRT_HIPCHK(expr)
+
+namespace dmrt {
+
+struct AdjointState {
+    long N = 0, K = 0, C = 0;
+    int nseg = 0;
+    size_t slot_elems = 0;       // 14 planes
+    void* ckpt = nullptr;        // nseg slots: s(k C)
+    void* seg = nullptr;         // C slots: s(k C + j)
+    void* lam = nullptr;         // 2 slots
+    double* nu_acc = nullptr;    // n
+    double* gthw = nullptr;      // n
+    double* grad0 = nullptr;     // n^2
+    double* sum = nullptr;       // 1
+    int* n0 = nullptr;           // 1
+    int* n0_table = nullptr;     // nseg
+    int win_start = 0;
+    bool forward_done = false;
+    double J = 0.0;
+    // graphs: forward units (plain / Nusselt-accumulating) by parity, and a
+    // full backward segment by lambda parity
+    static constexpr int kUnit = 50;
+    hipGraphExec_t fwd[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraph_t fwd_def[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t bwd[2] = {nullptr, nullptr};
+    hipGraph_t bwd_def[2] = {nullptr, nullptr};
+};
+
+void free_adjoint(AdjointState* a)
+{
+    if (!a) return;
+    for (int p = 0; p < 2; ++p) {
+        for (int v = 0; v < 2; ++v) {
+            if (a->fwd[p][v]) (void)hipGraphExecDestroy(a->fwd[p][v]);
+            if (a->fwd_def[p][v]) (void)hipGraphDestroy(a->fwd_def[p][v]);
+        }
+        if (a->bwd[p]) (void)hipGraphExecDestroy(a->bwd[p]);
+        if (a->bwd_def[p]) (void)hipGraphDestroy(a->bwd_def[p]);
+    }
+    void* ptrs[] = {a->ckpt, a->seg, a->lam, a->nu_acc, a->gthw, a->grad0, a->sum, a->n0, a->n0_table};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete a;
+}
+
+}  // namespace dmrt
+
+namespace {
+
+template <typename real>
+real* slot(void* base, size_t slot_elems, long i) { return static_cast<real*>(base) + (size_t)i * slot_elems; }
+
+template <typename real>
+StepArgs<real> step_args(const dmrt_cavity* h, const real* fin, const real* gin, real* fout, real* gout)
+{
+    StepArgs<real> A;
+    A.fin = fin; A.gin = gin; A.fout = fout; A.gout = gout;
+    A.thw = static_cast<const real*>(h->thw_real);
+    A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
+    A.tiles_x = (h->n + h->block_x - 1) / h->block_x;
+    A.tiles = A.tiles_x * ((h->n + h->block_y - 1) / h->block_y);
+    A.xcd_remap = h->xcd_remap;
+    A.c = make_coef<real>(h->p, h->d);
+    return A;
+}
+
+template <typename real>
+int launch_fwd(const dmrt_cavity* h, const AdjointState* a, hipStream_t s, const real* fin,
+               const real* gin, real* fout, real* gout, bool nu)
+{
+    const StepArgs<real> A = step_args<real>(h, fin, gin, fout, gout);
+    int nblocks = A.tiles;
+    if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
+    const dim3 grid(nblocks), block(h->block_x, h->block_y);
+    if (nu)
+        hipLaunchKernelGGL((step_nu_kernel<real>), grid, block, 0, s, A, h->thw_dbl, a->nu_acc);
+    else
+        hipLaunchKernelGGL((step_kernel<real, BC_CAVITY>), grid, block, 0, s, A);
+    HIPCHK(hipGetLastError());
+    return DMRT_OK;
+}
+
+template <typename real>
+real* cur_f(dmrt_cavity* h, int copy) { return static_cast<real*>(h->fbuf) + (size_t)copy * 9 * h->plane; }
+template <typename real>
+real* cur_g(dmrt_cavity* h, int copy) { return static_cast<real*>(h->gbuf) + (size_t)copy * 5 * h->plane; }
+
+// `count` forward steps on the cavity's ping-pong copies starting at `from`.
+template <typename real>
+int enqueue_fwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, int from, long count, bool nu)
+{
+    int c = from;
+    for (long i = 0; i < count; ++i) {
+        int rc = launch_fwd<real>(h, a, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),
+                                  cur_g<real>(h, c ^ 1), nu);
+        if (rc) return rc;
+        c ^= 1;
+    }
+    return DMRT_OK;
+}
+
+template <typename real>
+int run_fwd(dmrt_cavity* h, AdjointState* a, long count, bool nu)
+{
+    const int U = AdjointState::kUnit;
+    const int v = nu ? 1 : 0;
+    while (count >= U) {
+        if (!a->fwd[h->cur][v]) {
+            HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_fwd<real>(h, a, h->cap_stream, h->cur, U, nu);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+            if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+            if (e != hipSuccess) return record_hip(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&a->fwd[h->cur][v], g, nullptr, nullptr, 0);
+            if (e != hipSuccess) { (void)hipGraphDestroy(g); return record_hip(e, "hipGraphInstantiate"); }
+            a->fwd_def[h->cur][v] = g;
+        }
+        const long reps = count / U;
+        for (long r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(a->fwd[h->cur][v], h->stream));
+        count -= reps * U;              // U even: the copy index is unchanged
+    }
+    if (count > 0) {
+        int rc = enqueue_fwd<real>(h, a, h->stream, h->cur, count, nu);
+        if (rc) return rc;
+        if (count & 1) h->cur ^= 1;
+    }
+    return DMRT_OK;
+}
+
+// Backward work of one segment of `len` states starting at seg slot 0:
+// recompute slots 1..len-1, then adjoint steps j = len..1.
+template <typename real>
+int enqueue_bwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, long len, int lam_from)
+{
+    const size_t se = a->slot_elems;
+    const int P = h->plane;
+    for (long j = 1; j < len; ++j) {
+        real* src = slot<real>(a->seg, se, j - 1);
+        real* dst = slot<real>(a->seg, se, j);
+        int rc = launch_fwd<real>(h, a, s, src, src + 9 * (size_t)P, dst, dst + 9 * (size_t)P, false);
+        if (rc) return rc;
+    }
+    const double c = a->K > 0 ? h->d.H / (3.0 * (h->p.theta_hot - h->p.theta_cold) * h->n * a->K) : 0.0;
+    AdjArgs<real> A;
+    A.thw = static_cast<const real*>(h->thw_real);
+    A.gthw = a->gthw;
+    A.n0p = a->n0;
+    A.win_start = a->win_start;
+    A.seed0 = real(-9.0 * c);
+    A.seed1 = real(c);
+    A.cabb = (4.0 + h->d.a) / 10.0;
+    A.n = h->n; A.pitch = h->pitch; A.plane = P;
+    A.tiles_x = (h->n + h->block_x - 1) / h->block_x;
+    A.tiles = A.tiles_x * ((h->n + h->block_y - 1) / h->block_y);
+    A.c = make_coef<real>(h->p, h->d);
+    int l = lam_from;
+    for (long j = len; j >= 1; --j) {
+        real* st = slot<real>(a->seg, se, j - 1);
+        A.fs = st;
+        A.gs = st + 9 * (size_t)P;
+        A.lin = slot<real>(a->lam, se, l);
+        A.lout = slot<real>(a->lam, se, l ^ 1);
+        A.j = (int)j;
+        hipLaunchKernelGGL((adj_step_kernel<real>), dim3(A.tiles), dim3(h->block_x, h->block_y), 0, s, A);
+        HIPCHK(hipGetLastError());
+        l ^= 1;
+    }
+    return DMRT_OK;
+}
+
+int ensure_state(dmrt_cavity* h, long N, long K, long C)
+{
+    AdjointState* a = h->adj;
+    const int nseg = (int)((N + C - 1) / C);
+    if (a && a->N == N && a->K == K && a->C == C) return DMRT_OK;
+    if (a) { free_adjoint(a); h->adj = nullptr; }
+    a = new (std::nothrow) AdjointState();
+    if (!a) return DMRT_ENOMEM;
+    h->adj = a;
+    a->N = N; a->K = K; a->C = C; a->nseg = nseg;
+    a->slot_elems = 14 * (size_t)h->plane;
+    const size_t sb = a->slot_elems * h->esz;
+    const size_t nn = (size_t)h->n * h->n;
+    HIPCHK(hipMalloc(&a->ckpt, sb * nseg));
+    HIPCHK(hipMalloc(&a->seg, sb * C));
+    HIPCHK(hipMalloc(&a->lam, sb * 2));
+    HIPCHK(hipMemsetAsync(a->lam, 0, sb * 2, h->stream));
+    HIPCHK(hipMalloc(&a->nu_acc, h->n * sizeof(double)));
+    HIPCHK(hipMalloc(&a->gthw, h->n * sizeof(double)));
+    HIPCHK(hipMalloc(&a->grad0, nn * sizeof(double)));
+    HIPCHK(hipMalloc(&a->sum, sizeof(double)));
+    HIPCHK(hipMalloc(&a->n0, sizeof(int)));
+    HIPCHK(hipMalloc(&a->n0_table, nseg * sizeof(int)));
+    std::vector<int> t(nseg);
+    for (int k = 0; k < nseg; ++k) t[k] = (int)(k * C);
+    HIPCHK(hipMemcpyAsync(a->n0_table, t.data(), nseg * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return DMRT_OK;
+}
+
+template <typename real>
+int forward_t(dmrt_cavity* h, long N, long K, long C, double* J)
+{
+    int rc = ensure_state(h, N, K, C);
+    if (rc) return rc;
+    AdjointState* a = h->adj;
+    a->forward_done = false;
+    a->win_start = (int)(N - K + 1);
+    // re-initialise from the stored theta0 (rest state)
+    const dim3 ib(64, 4), ig((h->n + 63) / 64, (h->n + 3) / 4);
+    hipLaunchKernelGGL((init_kernel<real>), ig, ib, 0, h->stream, cur_f<real>(h, 0), cur_g<real>(h, 0),
+                       nullptr, nullptr, nullptr, h->theta0, h->n, h->pitch, h->plane,
+                       make_coef<real>(h->p, h->d), real(h->d.w0), real(h->d.wm));
+    HIPCHK(hipGetLastError());
+    h->cur = 0;
+    h->step = 0;
+    HIPCHK(hipMemsetAsync(a->nu_acc, 0, h->n * sizeof(double), h->stream));
+    const size_t P = h->plane, esz = h->esz;
+    for (int k = 0; k < a->nseg; ++k) {
+        char* ck = static_cast<char*>(a->ckpt) + (size_t)k * a->slot_elems * esz;
+        HIPCHK(hipMemcpyAsync(ck, cur_f<real>(h, h->cur), 9 * P * esz, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(ck + 9 * P * esz, cur_g<real>(h, h->cur), 5 * P * esz,
+                              hipMemcpyDeviceToDevice, h->stream));
+        const long first = (long)k * C + 1, last = std::min<long>((long)(k + 1) * C, N);
+        const long plain = std::max<long>(0, std::min<long>(last, a->win_start - 1) - first + 1);
+        const long with_nu = (last - first + 1) - plain;
+        if ((rc = run_fwd<real>(h, a, plain, false))) return rc;
+        if ((rc = run_fwd<real>(h, a, with_nu, true))) return rc;
+    }
+    h->step = N;
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, h->stream, a->nu_acc, h->n, a->sum);
+    HIPCHK(hipGetLastError());
+    double s = 0.0;
+    HIPCHK(hipMemcpyAsync(&s, a->sum, sizeof s, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    a->J = h->d.H / (3.0 * (h->p.theta_hot - h->p.theta_cold)) * s / ((double)h->n * K);
+    a->forward_done = true;
+    if (J) *J = a->J;
+    return DMRT_OK;
+}
+
+template <typename real>
+int backward_t(dmrt_cavity* h, double* gw, double* g0)
+{
+    AdjointState* a = h->adj;
+    const size_t se = a->slot_elems, esz = h->esz;
+    const double c = h->d.H / (3.0 * (h->p.theta_hot - h->p.theta_cold) * h->n * a->K);
+    const dim3 ib(64, 4), ig((h->n + 63) / 64, (h->n + 3) / 4);
+    // lambda(N) = dJ/ds(N); step N is always in the window
+    hipLaunchKernelGGL((adj_seed_kernel<real>), ig, ib, 0, h->stream, slot<real>(a->lam, se, 0), h->n,
+                       h->pitch, h->plane, real(-9.0 * c), real(c));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemsetAsync(a->gthw, 0, h->n * sizeof(double), h->stream));
+    int l = 0;
+    for (int k = a->nseg - 1; k >= 0; --k) {
+        const long len = std::min<long>(a->C, a->N - (long)k * a->C);
+        HIPCHK(hipMemcpyAsync(a->seg, static_cast<char*>(a->ckpt) + (size_t)k * se * esz, se * esz,
+                              hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(a->n0, a->n0_table + k, sizeof(int), hipMemcpyDeviceToDevice, h->stream));
+        if (len == a->C && a->C >= 2) {
+            if (!a->bwd[l]) {
+                HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+                int rc = enqueue_bwd<real>(h, a, h->cap_stream, len, l);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+                if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+                if (e != hipSuccess) return record_hip(e, "hipStreamEndCapture");
+                e = hipGraphInstantiate(&a->bwd[l], g, nullptr, nullptr, 0);
+                if (e != hipSuccess) { (void)hipGraphDestroy(g); return record_hip(e, "hipGraphInstantiate"); }
+                a->bwd_def[l] = g;
+            }
+            HIPCHK(hipGraphLaunch(a->bwd[l], h->stream));
+        } else {
+            int rc = enqueue_bwd<real>(h, a, h->stream, len, l);
+            if (rc) return rc;
+        }
+        if (len & 1) l ^= 1;
+    }
+    hipLaunchKernelGGL((adj_init_grad_kernel<real>), ig, ib, 0, h->stream, slot<real>(a->lam, se, l),
+                       h->theta0, h->n, h->pitch, h->plane, make_coef<real>(h->p, h->d), real(h->d.w0),
+                       real(h->d.wm), a->grad0);
+    HIPCHK(hipGetLastError());
+    const size_t nn = (size_t)h->n * h->n;
+    std::vector<double> tw(h->n);
+    HIPCHK(hipMemcpyAsync(tw.data(), a->gthw, h->n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (g0) HIPCHK(hipMemcpyAsync(g0, a->grad0, nn * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (gw) {
+        // direct dependence of Nu on theta_w (Eq. 18): 8 H / (3 dT n) per row
+        const double direct = 8.0 * h->d.H / (3.0 * (h->p.theta_hot - h->p.theta_cold) * h->n);
+        for (int y = 0; y < h->n; ++y) gw[y] = tw[y] + direct;
+    }
+    return DMRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dmrt_adjoint_forward(dmrt_cavity* h, long nsteps, long avg_last, long ckpt_every, double* J)
+{
+    if (!h || nsteps < 1 || avg_last < 1 || avg_last > nsteps || ckpt_every < 1) return DMRT_EINVAL;
+    if (nsteps > 2000000000L) return DMRT_EINVAL;
+    if (h->p.bc_mode != DMRT_BC_CAVITY || !h->theta0_valid) return DMRT_EINVAL;
+    if (!(h->p.theta_hot - h->p.theta_cold > 0.0)) return DMRT_EINVAL;
+    if (ckpt_every > nsteps) ckpt_every = nsteps;
+    return h->esz == 8 ? forward_t<double>(h, nsteps, avg_last, ckpt_every, J)
+                       : forward_t<float>(h, nsteps, avg_last, ckpt_every, J);
+}
+
+int dmrt_adjoint_backward(dmrt_cavity* h, double* dJ_dthetaw, double* dJ_dtheta0)
+{
+    if (!h || !h->adj || !h->adj->forward_done) return DMRT_EINVAL;
+    return h->esz == 8 ? backward_t<double>(h, dJ_dthetaw, dJ_dtheta0)
+                       : backward_t<float>(h, dJ_dthetaw, dJ_dtheta0);
+}
+
+int dmrt_adjoint_nu(dmrt_cavity* h, long nsteps, long avg_last, long ckpt_every, double* J,
+                    double* dJ_dthetaw, double* dJ_dtheta0)
+{
+    int rc = dmrt_adjoint_forward(h, nsteps, avg_last, ckpt_every, J);
+    if (rc) return rc;
+    return dmrt_adjoint_backward(h, dJ_dthetaw, dJ_dtheta0);
+}
+
+int dmrt_adjoint_release(dmrt_cavity* h)
+{
+    if (!h) return DMRT_EINVAL;
+    if (h->adj) {
+        (void)hipStreamSynchronize(h->stream);
+        free_adjoint(h->adj);
+        h->adj = nullptr;
+    }
+    return DMRT_OK;
+}
+
+}  // extern "C"

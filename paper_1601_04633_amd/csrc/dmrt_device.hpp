@@ -33,6 +33,14 @@ struct Coef {
     real cold;           // cabb * theta_cold
 };
 
+// Sum over a 64-wide wavefront (FP64).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // Pre-collision populations in, post-collision populations out (Eq. 25 and
 // Eq. 36 right-hand sides).  Moments of Eq. 30 and Eq. 37 are expanded into
 // the +-1/+-2/+-4 adds the matrices encode; the inverse transforms use
@@ -147,13 +155,13 @@ __device__ __forceinline__ int tile_of_block(int bid, int nblocks, int remap)
     return (bid & 7) * per + (bid >> 3);
 }
 
-// One node update (rows a1-a5): gather from the current copy with the wall
-// rules, collide in registers, store into the other copy.
+// Pull-streaming with the wall rules (row a1): f_i(r) = f*_i(r - e_i) when
+// r - e_i is inside, else the halfway bounce-back f*_opp(i)(r); for g the
+// same, with Eq. 44 on adiabatic walls and Eq. 45 on the isothermal walls.
 template <typename real, int BC>
-__device__ __forceinline__ void node_update(const real* __restrict__ fi, const real* __restrict__ gi,
-                                            real* __restrict__ fo, real* __restrict__ go,
-                                            const real* __restrict__ thw, int n, int pitch, int P,
-                                            int x, int y, const Coef<real>& c)
+__device__ __forceinline__ void gather(const real* __restrict__ fi, const real* __restrict__ gi,
+                                       const real* __restrict__ thw, int n, int pitch, int P,
+                                       int x, int y, const Coef<real>& c, real (&f)[9], real (&g)[5])
 {
     constexpr bool PX = (BC == BC_PERIODIC || BC == BC_CHANNEL_X);
     constexpr bool PY = (BC == BC_PERIODIC);
@@ -168,8 +176,6 @@ __device__ __forceinline__ void node_update(const real* __restrict__ fi, const r
     const int dym = (PY && y == 0) ? (n - 1) * pitch : -pitch;
     const int dyp = (PY && y == n - 1) ? -(n - 1) * pitch : pitch;
 
-    real f[9], g[5];
-    // pull: f_i(r) = f*_i(r - e_i), else bounce-back f*_opp(i)(r)
     f[0] = fi[k];
     f[1] = hxm ? fi[1 * P + k + dxm] : fi[3 * P + k];
     f[2] = hym ? fi[2 * P + k + dym] : fi[4 * P + k];
@@ -190,14 +196,31 @@ __device__ __forceinline__ void node_update(const real* __restrict__ fi, const r
         g[1] = hxm ? gi[1 * P + k + dxm] : gi[3 * P + k];
         g[3] = hxp ? gi[3 * P + k + dxp] : gi[1 * P + k];
     }
+}
 
+// One node update (rows a1-a5): gather from the current copy with the wall
+// rules, collide in registers, store into the other copy.  Returns the
+// node's temperature sum of the stored g* in FP64 (used only by the
+// Nusselt-accumulating variant; dead code elsewhere).
+template <typename real, int BC>
+__device__ __forceinline__ double node_update(const real* __restrict__ fi, const real* __restrict__ gi,
+                                              real* __restrict__ fo, real* __restrict__ go,
+                                              const real* __restrict__ thw, int n, int pitch, int P,
+                                              int x, int y, const Coef<real>& c)
+{
+    real f[9], g[5];
+    gather<real, BC>(fi, gi, thw, n, pitch, P, x, y, c, f, g);
     real th, ux, uy;
     collide<real>(f, g, c, th, ux, uy);
-
+    const int k = y * pitch + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) fo[i * P + k] = f[i];
 #pragma unroll
     for (int i = 0; i < 5; ++i) go[i * P + k] = g[i];
+    double ts = 0.0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) ts += double(g[i]);
+    return ts;
 }
 
 template <typename real, int BC>
@@ -211,6 +234,251 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<real> A)
     const int y = ty * blockDim.y + threadIdx.y;
     if (x >= A.n || y >= A.n) return;
     node_update<real, BC>(A.fin, A.gin, A.fout, A.gout, A.thw, A.n, A.pitch, A.plane, x, y, A.c);
+}
+
+// Cavity step that also accumulates, per row, the hot-wall Nusselt sum
+// 8 theta_w - 9 theta(0, y) + theta(1, y) of the new step (Eqs. 18-19) into
+// acc[y] in FP64 (one writer per row; launches are ordered).  Tiles start
+// at multiples of blockDim.x >= 64, so x = 0 and x = 1 share a wavefront.
+template <typename real>
+__global__ void __launch_bounds__(1024) step_nu_kernel(StepArgs<real> A, const double* __restrict__ thw_d,
+                                                       double* __restrict__ acc)
+{
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;
+    const int ty = tile / A.tiles_x;
+    const int tx = tile - ty * A.tiles_x;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y = ty * blockDim.y + threadIdx.y;
+    const bool valid = x < A.n && y < A.n;
+    double ts = 0.0;
+    if (valid)
+        ts = node_update<real, BC_CAVITY>(A.fin, A.gin, A.fout, A.gout, A.thw, A.n, A.pitch, A.plane,
+                                          x, y, A.c);
+    const double ts1 = __shfl_down(ts, 1, 64);
+    if (valid && x == 0) acc[y] += 8.0 * thw_d[y] - 9.0 * ts + ts1;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (reverse mode) of the step
+// ---------------------------------------------------------------------------
+// Vector-Jacobian product of collide() at the pre-collision state (f, g):
+// on entry lf, lg hold the adjoints of the post-collision populations, on
+// exit the adjoints of the pre-collision ones.  Derived by hand from the
+// moment form of collide(): the M^T reconstruction transposes into M
+// applied to lf (and N to lg); the relaxation, the equilibria of Eq. 34 and
+// Eq. 42 and the force image of Eq. 26 contribute through drho, u, v and
+// theta (G_y = gbeta theta + gy0).
+template <typename real>
+__device__ __forceinline__ void collide_vjp(const real (&f)[9], const real (&g)[5], const Coef<real>& c,
+                                            real (&lf)[9], real (&lg)[5])
+{
+    const real two = real(2), three = real(3), six = real(6);
+    const real u = (f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6]);
+    const real v = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+    const real theta = g[0] + (g[1] + g[3]) + (g[2] + g[4]);
+    const real uu = u * u, vv = v * v, q2 = uu + vv;
+    const real Gx = c.gx;
+    const real Gy = c.gbeta * theta + c.gy0;
+    const real Gu = Gx * u + Gy * v;
+    const real sn = c.s_nu, sq = c.s_q;
+
+    // adjoints of the moment changes: (M lf)_k / |row k|^2
+    const real l1234 = (lf[1] + lf[3]) + (lf[2] + lf[4]);
+    const real l5678 = (lf[5] + lf[7]) + (lf[6] + lf[8]);
+    const real L2 = ((lf[2] - lf[4]) + (lf[5] - lf[7]) + (lf[6] - lf[8])) * real(1.0 / 6.0);
+    const real L3 = (two * l5678 - l1234 - real(4) * lf[0]) * real(1.0 / 36.0);
+    const real L4 = ((lf[1] + lf[3]) - (lf[2] + lf[4])) * real(0.25);
+    const real L5 = ((lf[5] + lf[7]) - (lf[6] + lf[8])) * real(0.25);
+    const real L6 = (two * (lf[3] - lf[1]) + (lf[5] - lf[7]) + (lf[8] - lf[6])) * real(1.0 / 12.0);
+    const real L7 = (two * (lf[4] - lf[2]) + (lf[5] - lf[7]) + (lf[6] - lf[8])) * real(1.0 / 12.0);
+    const real L8 = (real(4) * lf[0] - two * l1234 + l5678) * real(1.0 / 36.0);
+
+    // through the non-conserved moments (relaxation)
+    const real mu3 = -sn * L3, mu4 = -sn * L4, mu5 = -sn * L5;
+    const real mu6 = -sq * L6, mu7 = -sq * L7, mu8 = -sn * L8;
+    // through drho (energy equilibria)
+    const real ldrho = sn * (L8 - two * L3);
+    // through u and v (equilibria and force image)
+    const real L38 = L3 - L8;
+    const real dF3du = three * Gx * (two - three * q2) - real(18) * u * Gu;
+    const real dF3dv = three * Gy * (two - three * q2) - real(18) * v * Gu;
+    const real dF4du = Gx * (two - real(9) * uu + three * vv) - six * Gy * u * v;
+    const real dF4dv = six * Gx * u * v - Gy * (two + three * uu - real(9) * vv);
+    const real dF5du = Gy * (real(1) - three * vv) - six * Gx * u * v;
+    const real dF5dv = Gx * (real(1) - three * uu) - six * Gy * u * v;
+    real lu = L38 * (dF3du + six * sn * u) + L4 * (dF4du + two * sn * u) + L5 * (dF5du + sn * v) +
+              L6 * (six * Gy * v - sq) + L7 * (six * (Gx * v + Gy * u));
+    real lv = L38 * (dF3dv + six * sn * v) + L4 * (dF4dv - two * sn * v) + L5 * (dF5dv + sn * u) +
+              L6 * (six * (Gy * u + Gx * v)) + L7 * (six * Gx * u - sq);
+    // through G_y (buoyancy of Eq. 27)
+    const real lGy = L2 + L38 * three * v * (two - three * q2) - L4 * v * (two + three * uu - three * vv) +
+                     L5 * u * (real(1) - three * vv) + L6 * six * u * v - L7 * (real(1) - three * uu);
+
+    // D2Q5: adjoints of the moment changes (N lg)_k / |row k|^2
+    const real K1 = (lg[1] - lg[3]) * real(0.5);
+    const real K2 = (lg[2] - lg[4]) * real(0.5);
+    const real K3 = ((lg[1] + lg[3]) + (lg[2] + lg[4]) - real(4) * lg[0]) * real(0.05);
+    const real K4 = ((lg[1] + lg[3]) - (lg[2] + lg[4])) * real(0.25);
+    const real ln1 = -c.sk * K1, ln2 = -c.sk * K2, ln3 = -c.se * K3, ln4 = -c.sn * K4;
+    lu += c.sk * theta * K1;
+    lv += c.sk * theta * K2;
+    const real lth = c.sk * (u * K1 + v * K2) + c.se * c.a * K3 + c.gbeta * lGy;
+
+    // pre-collision adjoints: identity + M^T (moment adjoints) + N^T (...)
+    const real d2 = two * mu3 + mu8;
+    lf[0] += ldrho + real(4) * (mu8 - mu3);
+    lf[1] += ldrho + lu - mu3 + mu4 - two * mu6 - two * mu8;
+    lf[2] += ldrho + lv - mu3 - mu4 - two * mu7 - two * mu8;
+    lf[3] += ldrho - lu - mu3 + mu4 + two * mu6 - two * mu8;
+    lf[4] += ldrho - lv - mu3 - mu4 + two * mu7 - two * mu8;
+    lf[5] += ldrho + d2 + (lu + lv) + (mu5 + mu6 + mu7);
+    lf[6] += ldrho + d2 + (lv - lu) + (mu7 - mu5 - mu6);
+    lf[7] += ldrho + d2 - (lu + lv) + (mu5 - mu6 - mu7);
+    lf[8] += ldrho + d2 + (lu - lv) + (mu6 - mu5 - mu7);
+    lg[0] += lth - real(4) * ln3;
+    lg[1] += lth + ln1 + ln3 + ln4;
+    lg[2] += lth + ln2 + ln3 - ln4;
+    lg[3] += lth - ln1 + ln3 + ln4;
+    lg[4] += lth - ln2 + ln3 - ln4;
+}
+
+template <typename real>
+struct AdjArgs {
+    const real* __restrict__ fs;     // s(n-1): f planes
+    const real* __restrict__ gs;     // s(n-1): g planes
+    const real* __restrict__ lin;    // lambda(n): 14 planes (f then g)
+    real* __restrict__ lout;         // lambda(n-1)
+    const real* __restrict__ thw;
+    double* __restrict__ gthw;       // accumulates dJ/dtheta_w (anti-bounce-back links)
+    const int* __restrict__ n0p;     // step index of the segment's first state
+    int j;                           // this launch is the adjoint of step *n0p + j
+    int win_start;                   // first step of the objective window
+    real seed0, seed1;               // dJ/dg*_i(m) at x = 0 and x = 1 for m in the window
+    double cabb;                     // Eq. 45 constant in FP64
+    int n, pitch, plane, tiles_x, tiles;
+    Coef<real> c;
+};
+
+// Adjoint of step n for the cavity: lambda(n-1) = S^T C'(p(n))^T lambda(n)
+// + dJ/ds(n-1), with p(n) the pre-collision state gathered from s(n-1)
+// exactly as in the forward step, S the streaming/wall map.  S is a
+// permutation (with sign -1 on the anti-bounce-back links), so the
+// transposed streaming is a push: every lambda(n-1) entry has exactly one
+// writer.  The anti-bounce-back constant's derivative feeds dJ/dtheta_w.
+template <typename real>
+__global__ void __launch_bounds__(1024) adj_step_kernel(AdjArgs<real> A)
+{
+    const int tile = blockIdx.x;
+    if (tile >= A.tiles) return;
+    const int ty = tile / A.tiles_x;
+    const int tx = tile - ty * A.tiles_x;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y = ty * blockDim.y + threadIdx.y;
+    const int n = A.n;
+    if (x >= n || y >= n) return;
+    const int pitch = A.pitch, P = A.plane;
+    const int k = y * pitch + x;
+
+    real f[9], g[5];
+    gather<real, BC_CAVITY>(A.fs, A.gs, A.thw, n, pitch, P, x, y, A.c, f, g);
+    real lf[9], lg[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lf[i] = A.lin[i * P + k];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lg[i] = A.lin[(9 + i) * P + k];
+    collide_vjp<real>(f, g, A.c, lf, lg);
+
+    const int m = *A.n0p + A.j - 1;                 // lambda(m) is being formed
+    const bool win = m >= A.win_start;
+    const real s0 = win ? A.seed0 : real(0), s1 = win ? A.seed1 : real(0);
+
+    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
+    real* __restrict__ lo = A.lout;
+    // D2Q9: the population that arrived from r - e_i, or bounced at r
+    lo[k] = lf[0];
+    if (hxm) lo[1 * P + k - 1] = lf[1]; else lo[3 * P + k] = lf[1];
+    if (hym) lo[2 * P + k - pitch] = lf[2]; else lo[4 * P + k] = lf[2];
+    if (hxp) lo[3 * P + k + 1] = lf[3]; else lo[1 * P + k] = lf[3];
+    if (hyp) lo[4 * P + k + pitch] = lf[4]; else lo[2 * P + k] = lf[4];
+    if (hxm && hym) lo[5 * P + k - pitch - 1] = lf[5]; else lo[7 * P + k] = lf[5];
+    if (hxp && hym) lo[6 * P + k - pitch + 1] = lf[6]; else lo[8 * P + k] = lf[6];
+    if (hxp && hyp) lo[7 * P + k + pitch + 1] = lf[7]; else lo[5 * P + k] = lf[7];
+    if (hxm && hyp) lo[8 * P + k + pitch - 1] = lf[8]; else lo[6 * P + k] = lf[8];
+    // D2Q5, plus the temperature seed of the Nusselt objective on the two
+    // columns next to the hot wall
+    real* __restrict__ lg_o = lo + 9 * P;
+    const real sx = x == 0 ? s0 : (x == 1 ? s1 : real(0));
+    const real sxm = x == 1 ? s0 : (x == 2 ? s1 : real(0));   // node x - 1
+    const real sxp = x == 0 ? s1 : real(0);                     // node x + 1
+    lg_o[k] = lg[0] + sx;
+    if (hxm) lg_o[1 * P + k - 1] = lg[1] + sxm;
+    else {
+        lg_o[3 * P + k] = sx - lg[1];                           // Eq. 45, left wall
+        A.gthw[y] += A.cabb * double(lg[1]);
+    }
+    if (hxp) lg_o[3 * P + k + 1] = lg[3] + sxp;
+    else lg_o[1 * P + k] = sx - lg[3];                          // Eq. 45, right wall
+    if (hym) lg_o[2 * P + k - pitch] = lg[2] + sx; else lg_o[4 * P + k] = lg[2] + sx;
+    if (hyp) lg_o[4 * P + k + pitch] = lg[4] + sx; else lg_o[2 * P + k] = lg[4] + sx;
+}
+
+// lambda(N) = dJ/ds(N): zero except the temperature seed next to the hot wall.
+template <typename real>
+__global__ void adj_seed_kernel(real* __restrict__ lam, int n, int pitch, int plane, real seed0,
+                                real seed1)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= n || y >= n) return;
+    const int k = y * pitch + x;
+    const real s = x == 0 ? seed0 : (x == 1 ? seed1 : real(0));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lam[i * plane + k] = real(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lam[(9 + i) * plane + k] = s;
+}
+
+// dJ/dtheta0 from lambda(0): the initial pre-collision state is f = 0,
+// g_i = w_i theta0, so dJ/dtheta0 = sum_i w_i (C'(p(0))^T lambda(0))_g,i.
+template <typename real>
+__global__ void adj_init_grad_kernel(const real* __restrict__ lam, const double* __restrict__ theta0,
+                                     int n, int pitch, int plane, Coef<real> c, real w0, real wm,
+                                     double* __restrict__ grad)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= n || y >= n) return;
+    const int k = y * pitch + x;
+    const real th = real(theta0[y * n + x]);
+    real f[9], g[5], lf[9], lg[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { f[i] = real(0); lf[i] = lam[i * plane + k]; }
+    g[0] = w0 * th;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) g[i] = wm * th;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lg[i] = lam[(9 + i) * plane + k];
+    collide_vjp<real>(f, g, c, lf, lg);
+    grad[y * n + x] = double(w0) * double(lg[0]) +
+                      double(wm) * (double(lg[1]) + double(lg[2]) + double(lg[3]) + double(lg[4]));
+}
+
+// Sum of n doubles by one workgroup (FP64).
+static __global__ void __launch_bounds__(256) sum_kernel(const double* __restrict__ a, int n,
+                                                   double* __restrict__ out)
+{
+    __shared__ double part[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += a[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+        *out = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -329,12 +597,6 @@ __global__ void fields_kernel(const real* __restrict__ fs, const real* __restric
 // ---------------------------------------------------------------------------
 // Wall Nusselt number, Eqs. 18-19: one workgroup, FP64 accumulation.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // Sum over the rows of the local Nusselt numbers of one wall, by one
 // workgroup of 256 threads; returns the average to thread 0.

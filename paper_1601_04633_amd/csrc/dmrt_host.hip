@@ -121,40 +121,6 @@ struct DeviceGuard {
 
 }  // namespace
 
-struct dmrt_cavity {
-    dmrt_params p;
-    dmrt_derived d;
-    int dev = 0;
-    int n = 0, pitch = 0, plane = 0;
-    size_t esz = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    hipStream_t cap_stream = nullptr;
-    void* fbuf = nullptr;     // [2][9][plane]
-    void* gbuf = nullptr;     // [2][5][plane]
-    bool own_bufs = false;
-    int cur = 0;              // copy holding the current state
-    long step = 0;
-    // hot wall
-    void* thw_real = nullptr;         // n reals
-    double* thw_dbl = nullptr;        // n doubles
-    std::vector<double> thw_host;
-    // diagnostics scratch
-    double* scratch = nullptr;        // fields upload / download, 4 n^2 doubles
-    double* nu_buf = nullptr;         // n + 1 doubles
-    double* res_ref = nullptr;        // 3 n^2 doubles
-    double* res_part = nullptr;       // residual partials
-    int res_blocks = 0;
-    double* ring = nullptr;
-    unsigned long long* ring_count = nullptr;
-    long ring_cap = 0;
-    int series_stride = 0;
-    // launch
-    int block_x = 256, block_y = 1, xcd_remap = 1, graph_steps = 64;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
-    hipGraph_t graph_def[2] = {nullptr, nullptr};
-};
-
 namespace {
 
 void drop_graphs(dmrt_cavity* h)
@@ -452,6 +418,18 @@ int dmrt_set_equilibrium(dmrt_cavity* h, const double* drho, const double* U, co
     rc = h->esz == sizeof(double) ? launch_init_t<double>(h, dptr[0], dptr[1], dptr[2], dptr[3])
                                   : launch_init_t<float>(h, dptr[0], dptr[1], dptr[2], dptr[3]);
     if (rc) return rc;
+    // a rest state with a temperature field is the initial condition of the
+    // gradient problem: keep theta0 on the device
+    h->theta0_valid = false;
+    if (!drho && !U && !V) {
+        if (!h->theta0) HIPCHK(hipMalloc(&h->theta0, nn * sizeof(double)));
+        if (theta)
+            HIPCHK(hipMemcpyAsync(h->theta0, dptr[3], nn * sizeof(double), hipMemcpyDeviceToDevice,
+                                  h->stream));
+        else
+            HIPCHK(hipMemsetAsync(h->theta0, 0, nn * sizeof(double), h->stream));
+        h->theta0_valid = true;
+    }
     h->cur = 0;
     h->step = 0;
     if ((rc = reset_series(h))) return rc;
@@ -719,6 +697,7 @@ int dmrt_set_launch(dmrt_cavity* h, int block_x, int block_y, int xcd_remap, int
     DeviceGuard g(h->dev);
     HIPCHK(hipStreamSynchronize(h->stream));
     drop_graphs(h);
+    if (h->adj) { free_adjoint(h->adj); h->adj = nullptr; }   // its graphs bake the shape
     h->block_x = block_x;
     h->block_y = block_y;
     h->xcd_remap = xcd_remap;
@@ -742,8 +721,9 @@ int dmrt_destroy(dmrt_cavity* h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     drop_graphs(h);
     if (h->own_bufs) { (void)hipFree(h->fbuf); (void)hipFree(h->gbuf); }
+    if (h->adj) free_adjoint(h->adj);
     void* ptrs[] = {h->thw_real, h->thw_dbl, h->scratch, h->nu_buf, h->res_ref, h->res_part,
-                    h->ring, h->ring_count};
+                    h->ring, h->ring_count, h->theta0};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);

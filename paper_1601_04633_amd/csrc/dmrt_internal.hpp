@@ -38,7 +38,51 @@ Coef<real> make_coef(const dmrt_params& p, const dmrt_derived& d)
 // Thread-local text of the last HIP error.
 void set_last_error(const char* msg);
 
+struct AdjointState;          // dmrt_adjoint.hip
+void free_adjoint(AdjointState* a);
+
 }  // namespace dmrt
+
+#include <vector>
+
+struct dmrt_cavity {
+    dmrt_params p;
+    dmrt_derived d;
+    int dev = 0;
+    int n = 0, pitch = 0, plane = 0;
+    size_t esz = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    void* fbuf = nullptr;     // [2][9][plane]
+    void* gbuf = nullptr;     // [2][5][plane]
+    bool own_bufs = false;
+    int cur = 0;              // copy holding the current state
+    long step = 0;
+    // hot wall
+    void* thw_real = nullptr;         // n reals
+    double* thw_dbl = nullptr;        // n doubles
+    std::vector<double> thw_host;
+    // diagnostics scratch
+    double* scratch = nullptr;        // fields upload / download, 4 n^2 doubles
+    double* nu_buf = nullptr;         // n + 1 doubles
+    double* res_ref = nullptr;        // 3 n^2 doubles
+    double* res_part = nullptr;       // residual partials
+    int res_blocks = 0;
+    double* ring = nullptr;
+    unsigned long long* ring_count = nullptr;
+    long ring_cap = 0;
+    int series_stride = 0;
+    // launch
+    int block_x = 256, block_y = 1, xcd_remap = 1, graph_steps = 64;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraph_t graph_def[2] = {nullptr, nullptr};
+    // initial temperature of the last dmrt_set_theta (gradient problem)
+    double* theta0 = nullptr;         // n^2 doubles
+    bool theta0_valid = false;
+    dmrt::AdjointState* adj = nullptr;
+};
+
 
 #define DMRT_HIPCHK(expr)                                          \
     do {                                                           \

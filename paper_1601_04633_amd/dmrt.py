@@ -95,6 +95,10 @@ _SIGS = {
     "dmrt_set_launch": [_vp, _c_int, _c_int, _c_int, _c_int],
     "dmrt_buffers": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_c_int)],
     "dmrt_destroy": [_vp],
+    "dmrt_adjoint_forward": [_vp, _c_long, _c_long, _c_long, _dp],
+    "dmrt_adjoint_backward": [_vp, _dp, _dp],
+    "dmrt_adjoint_nu": [_vp, _c_long, _c_long, _c_long, _dp, _dp, _dp],
+    "dmrt_adjoint_release": [_vp],
     "dmrt_batch_create": [_P, _c_int, _vp, ctypes.POINTER(_vp)],
     "dmrt_batch_set_theta": [_vp, _c_int, _dp],
     "dmrt_batch_set_hot_wall": [_vp, _c_int, _dp],
@@ -302,6 +306,30 @@ class Cavity:
 
     def set_launch(self, block_x=256, block_y=1, xcd_remap=1, graph_steps=64):
         check(dmrt_set_launch(self._h, block_x, block_y, xcd_remap, graph_steps), "dmrt_set_launch")
+
+    # -- gradient of the time-averaged hot-wall Nusselt number ------------------
+    def adjoint_forward(self, nsteps, avg_last, ckpt_every=500):
+        J = ctypes.c_double(0.0)
+        check(dmrt_adjoint_forward(self._h, int(nsteps), int(avg_last), int(ckpt_every),
+                                   ctypes.byref(J)), "dmrt_adjoint_forward")
+        return J.value
+
+    def adjoint_backward(self):
+        gw = np.empty(self.n)
+        g0 = np.empty(self.n * self.n)
+        check(dmrt_adjoint_backward(self._h, _ptr(gw), _ptr(g0)), "dmrt_adjoint_backward")
+        return gw, g0.reshape(self.n, self.n)
+
+    def adjoint_nu(self, nsteps, avg_last, ckpt_every=500):
+        J = ctypes.c_double(0.0)
+        gw = np.empty(self.n)
+        g0 = np.empty(self.n * self.n)
+        check(dmrt_adjoint_nu(self._h, int(nsteps), int(avg_last), int(ckpt_every), ctypes.byref(J),
+                              _ptr(gw), _ptr(g0)), "dmrt_adjoint_nu")
+        return J.value, gw, g0.reshape(self.n, self.n)
+
+    def adjoint_release(self):
+        check(dmrt_adjoint_release(self._h), "dmrt_adjoint_release")
 
     def buffers(self):
         f, g, c = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int(0)

@@ -1,0 +1,157 @@
+"""GPU tests of the hand-written adjoint (gradient of the time-averaged
+hot-wall Nusselt number with respect to the hot-wall profile and the initial
+temperature field):
+
+* one step, and a few hundred steps with several checkpoint segments, against
+  the CPU reference gradient (automatic differentiation of a vectorised FP64
+  restatement of the oracle; oracle/torch_ref.py);
+* the 32^2, 10,000-step instance against FP64 central differences of the C
+  oracle (h = 1e-6): all 32 hot-wall entries, 64 initial-field entries and 4
+  random directions;
+* independence of the checkpoint interval (bitwise), the FP32 path at the
+  256^2 configuration against the FP64 one, and the autograd Function.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_1601_04633_amd import inputs
+
+
+def _cavity(n, Ra, Pr, precision="fp64", **kw):
+    from paper_1601_04633_amd.dmrt import Cavity
+    return Cavity(n=n, Ra=Ra, Pr=Pr, precision=precision, **kw)
+
+
+def _gpu_grad(n, Ra, Pr, tw, t0, N, K, C, precision="fp64"):
+    c = _cavity(n, Ra, Pr, precision)
+    c.set_hot_wall(tw)
+    c.set_theta(t0)
+    J, gw, g0 = c.adjoint_nu(N, K, C)
+    c.close()
+    return J, gw, g0
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+@pytest.mark.parametrize("n", [16, 37])
+def test_single_step_against_reference(n):
+    from oracle.torch_ref import Reference
+    print(f"[adjoint] single step n={n}", flush=True)
+    tw = inputs.hot_wall_profile(n, 21)
+    t0 = inputs.theta_noise(n, 22, amp=0.05)
+    Jg, gw, g0 = _gpu_grad(n, 1e4, 0.01, tw, t0, 1, 1, 1)
+    Jr, rw, r0 = Reference(n, 1e4, 0.01).gradient(tw, t0, 1, 1)
+    assert abs(Jg - Jr) <= 1e-13 * abs(Jr)
+    assert rel(gw, rw) <= 1e-12 and rel(g0, r0) <= 1e-12
+
+
+@pytest.mark.parametrize("n,N,K,C", [(32, 600, 150, 100), (40, 333, 333, 64)])
+def test_many_steps_against_reference(n, N, K, C):
+    from oracle.torch_ref import Reference
+    print(f"[adjoint] n={n} N={N} K={K} C={C}", flush=True)
+    tw = inputs.hot_wall_profile(n, 23)
+    t0 = inputs.theta_noise(n, 24, amp=1e-2)
+    Jg, gw, g0 = _gpu_grad(n, 1e4, 0.01, tw, t0, N, K, C)
+    Jr, rw, r0 = Reference(n, 1e4, 0.01).gradient(tw, t0, N, K, segment=100)
+    assert abs(Jg - Jr) <= 1e-12 * abs(Jr)
+    assert rel(gw, rw) <= 1e-10, rel(gw, rw)
+    assert rel(g0, r0) <= 1e-10, rel(g0, r0)
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    n, N, K = 24, 300, 100
+    tw = inputs.hot_wall_profile(n, 25)
+    t0 = inputs.theta_noise(n, 26, amp=1e-2)
+    ref = None
+    for C in (1, 7, 50, 300):
+        out = _gpu_grad(n, 1e4, 0.01, tw, t0, N, K, C)
+        if ref is None:
+            ref = out
+        else:
+            assert out[0] == ref[0]
+            assert np.array_equal(out[1], ref[1]) and np.array_equal(out[2], ref[2]), C
+
+
+def test_fp64_adjoint_against_oracle_finite_differences(oracle_mod):
+    """The 32^2 instance (Ra 1e4, Pr 0.01, FP64, 10,000 steps, mean Nu over
+    the last 2,000, checkpoints every 500): adjoint gradients against
+    central differences (h = 1e-6) of the C oracle's objective."""
+    from oracle import fd
+    n, Ra, Pr, N, K, C = 32, 1e4, 0.01, 10000, 2000, 500
+    tw = inputs.hot_wall_profile(n, 1601)
+    t0 = inputs.theta_noise(n, 1601)
+    print("[adjoint] fd check 32^2 10000 steps", flush=True)
+    Jg, gw, g0 = _gpu_grad(n, Ra, Pr, tw, t0, N, K, C)
+    o = oracle_mod.Oracle(n, Ra, Pr)
+    o.set_hot_wall(tw)
+    o.set_theta(t0)
+    Jo = o.objective(N, K)
+    assert abs(Jg - Jo) <= 1e-12 * abs(Jo)
+    rng = np.random.default_rng(1601)
+    # (a) every hot-wall entry and 4 random directions, h = 1e-6
+    dirs, adj = [], []
+    for y in range(n):
+        dirs.append((np.eye(n)[y], np.zeros((n, n))))
+        adj.append(gw[y])
+    dw_all = inputs.random_directions((n,), 4, 77)
+    d0_all = inputs.random_directions((n, n), 4, 78)
+    for dw, d0 in zip(dw_all, d0_all):
+        dirs.append((dw / np.sqrt(2), d0 / np.sqrt(2)))
+        adj.append(((gw * dw).sum() + (g0 * d0).sum()) / np.sqrt(2))
+    got = np.array(fd.directional_derivatives(n, Ra, Pr, tw, t0, N, K, dirs, h=1e-6, workers=16))
+    adj = np.array(adj)
+    rel_a = np.abs(adj - got) / np.abs(got)
+    print(f"[adjoint] fd (theta_w, directions; h 1e-6): max rel err {rel_a.max():.3e}", flush=True)
+    assert rel_a.max() <= 1e-6, rel_a.max()
+    # (b) 64 initial-field entries.  After 10,000 steps these derivatives are
+    # 1e-9..2e-5, below the round-off of a central difference at h = 1e-6;
+    # J is linear in theta0 to ~1e-9 at h = 1e-2, whose round-off floor is
+    # ~2e-13 absolute.
+    dirs, adj = [], []
+    for idx in rng.choice(n * n, size=64, replace=False):
+        d0 = np.zeros(n * n)
+        d0[idx] = 1.0
+        dirs.append((np.zeros(n), d0.reshape(n, n)))
+        adj.append(g0.reshape(-1)[idx])
+    got = np.array(fd.directional_derivatives(n, Ra, Pr, tw, t0, N, K, dirs, h=1e-2, workers=16))
+    adj = np.array(adj)
+    err = np.abs(adj - got)
+    print(f"[adjoint] fd (theta0; h 1e-2): max rel err {(err / np.abs(got)).max():.3e}, "
+          f"max abs err {err.max():.3e}, |grad| {np.abs(got).min():.2e}..{np.abs(got).max():.2e}",
+          flush=True)
+    assert np.all(err <= 1e-6 * np.abs(got) + 1e-12)
+
+
+def test_fp32_adjoint_config_against_fp64():
+    """256^2, Ra 1e4, Pr 0.01, 10,000 steps, mean Nu over the last 2,000,
+    checkpoints every 500: the FP32 path against the FP64 path."""
+    n, Ra, Pr, N, K, C = 256, 1e4, 0.01, 10000, 2000, 500
+    tw = inputs.hot_wall_profile(n, 4633)
+    t0 = inputs.theta_noise(n, 1601)
+    print("[adjoint] fp32 vs fp64 256^2", flush=True)
+    J32, w32, z32 = _gpu_grad(n, Ra, Pr, tw, t0, N, K, C, "fp32")
+    J64, w64, z64 = _gpu_grad(n, Ra, Pr, tw, t0, N, K, C, "fp64")
+    print(f"[adjoint] fp32 vs fp64: J {abs(J32 - J64) / abs(J64):.2e}, dJ/dtheta_w "
+          f"{rel(w32, w64):.2e}, dJ/dtheta0 {rel(z32, z64):.2e}", flush=True)
+    assert abs(J32 - J64) <= 1e-4 * abs(J64)
+    assert rel(w32, w64) <= 1e-3
+    assert rel(z32, z64) <= 1e-2
+
+
+def test_autograd_function():
+    import torch
+    from paper_1601_04633_amd.adjoint import nu_objective
+    n, N, K, C = 32, 400, 100, 50
+    tw = torch.tensor(inputs.hot_wall_profile(n, 27), requires_grad=True)
+    t0 = torch.tensor(inputs.theta_noise(n, 28, amp=1e-2), requires_grad=True)
+    c = _cavity(n, 1e4, 0.01)
+    J = nu_objective(tw, t0, c, N, K, C)
+    (2.0 * J).backward()
+    Jd, gw, g0 = _gpu_grad(n, 1e4, 0.01, tw.detach().numpy(), t0.detach().numpy(), N, K, C)
+    assert float(J) == Jd
+    assert np.array_equal(tw.grad.numpy(), 2.0 * gw)
+    assert np.array_equal(t0.grad.numpy(), 2.0 * g0)
