@@ -154,6 +154,51 @@ def bench_batch(steps, single_steps, count=64, seed=4633, tune=True):
             "nu_hot_wall_mean": float(nu[np.isfinite(nu)].mean())}
 
 
+def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp32"):
+    """Gradient of the mean hot-wall Nu over the last K of N steps (256^2,
+    FP32, checkpoints every C): time per step of the plain forward, of the
+    checkpointed forward that also accumulates J, and of the backward
+    (segment recompute + adjoint kernel)."""
+    import torch
+    from paper_1601_04633_amd import inputs
+    from paper_1601_04633_amd.dmrt import Cavity
+    stream = torch.cuda.Stream()
+    c = Cavity(n=n, Ra=Ra, Pr=Pr, precision=precision, stream=stream.cuda_stream)
+    tw = inputs.hot_wall_profile(n, 4633)
+    t0 = inputs.theta_noise(n, 1601)
+    c.set_hot_wall(tw)
+    c.set_theta(t0)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        e1.synchronize()
+        return out, e0.elapsed_time(e1) * 1e-3
+
+    c.step(1000)                                  # warm-up, graphs
+    c.sync()
+    _, t_plain = timed(lambda: c.step(N))
+    c.adjoint_forward(N, K, C)                     # warm-up: buffers and graphs
+    c.adjoint_backward()
+    J, t_fwd = timed(lambda: c.adjoint_forward(N, K, C))
+    (gw, g0), t_bwd = timed(lambda: c.adjoint_backward())
+    c.close()
+    return {"workload": f"{n}x{n} cavity, Ra={Ra:g}, Pr={Pr:g}, {precision.upper()}, {N} steps, "
+                        f"J = mean hot-wall Nu over the last {K}, checkpoint every {C}",
+            "forward_us_per_step": round(t_plain / N * 1e6, 3),
+            "checkpointed_forward_us_per_step": round(t_fwd / N * 1e6, 3),
+            "backward_us_per_step": round(t_bwd / N * 1e6, 3),
+            "backward_over_forward": round(t_bwd / t_plain, 3),
+            "forward_plus_backward_over_forward": round((t_fwd + t_bwd) / t_plain, 3),
+            "ideal_backward_over_forward_bytes": 2.5,
+            "J": J, "grad_theta_w_norm": float(np.linalg.norm(gw)),
+            "grad_theta0_norm": float(np.linalg.norm(g0))}
+
+
 def cpu_baseline(n, Ra, Pr, budget_s=15.0):
     """The FP64 oracle on the host (single thread) over a bounded sample of
     the same workload: whole steps of the same cavity until ~budget_s."""
@@ -186,6 +231,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,xcd_remap,graph_steps")
+    ap.add_argument("--sections", default="main,extras,batch,adjoint,cpu",
+                    help="comma list of main, extras, batch, adjoint, cpu")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--single-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -248,7 +295,13 @@ def main():
         out["calib_copy_bytes_each_way"] = src.numel() * 4
         log("calibration copy: 5 x 256 MiB")
 
-    if not args.no_extras:
+    sections = set(args.sections.split(","))
+    if args.no_extras:
+        sections -= {"extras", "batch", "adjoint"}
+    if args.no_cpu:
+        sections -= {"cpu"}
+
+    if "extras" in sections:
         extras = {}
         log("extra: fp64 same cavity")
         _, m64, l64, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1000), 500)
@@ -259,12 +312,18 @@ def main():
         extras["fp32_2048_mlups"] = round(m2k, 1)
         extras["fp32_2048_hbm_frac"] = round(112 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         out["extras"] = extras
+    if "batch" in sections:
         log("batch: 64-cavity Ra x Pr sweep vs one by one")
         out["batch"] = bench_batch(args.batch_steps, args.single_steps)
         log(f"batch: {out['batch']['batch_mlups']} MLUPS vs one by one "
             f"{out['batch']['one_by_one_mlups']} MLUPS")
 
-    if not args.no_cpu:
+    if "adjoint" in sections:
+        log("adjoint: 256^2 FP32 gradient of the mean hot-wall Nu")
+        out["adjoint"] = bench_adjoint()
+        log(f"adjoint: backward/forward {out['adjoint']['backward_over_forward']}")
+
+    if "cpu" in sections:
         log("cpu baseline (oracle, single thread)")
         out["cpu_baseline"] = cpu_baseline(n, Ra, Pr)
     print(json.dumps(out), flush=True)

@@ -7,12 +7,14 @@
 // steps; the state is copied to a checkpoint every C steps, and on the last
 // K steps a variant of the step kernel accumulates each row's Nusselt sum in
 // FP64.  J = H / (3 dT n K) * sum over rows and window steps.
-// Backward: for each segment of C steps, newest first, the states of the
-// segment are recomputed from its checkpoint into a segment buffer, then
-// the adjoint step kernel runs from the segment's last step to its first
-// (lambda ping-pong).  A captured graph of one full segment is replayed for
-// every full segment; the segment's first step index is read from device
-// memory, which is updated before each replay.
+// Backward: segments of C steps, newest first.  Each segment's states are
+// recomputed from its checkpoint into one of two segment buffers; the
+// adjoint step kernel then runs from the segment's last step to its first
+// (lambda ping-pong), and each of its launches also carries one recompute
+// step of the next-older segment into the other buffer (independent work,
+// so the small per-step launches fill the chip).  A captured graph of one
+// full segment is replayed for every full segment; the segment's first step
+// index is read from device memory, updated before each replay.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,7 +37,7 @@ struct AdjointState {
     int nseg = 0;
     size_t slot_elems = 0;       // 14 planes
     void* ckpt = nullptr;        // nseg slots: s(k C)
-    void* seg = nullptr;         // C slots: s(k C + j)
+    void* seg[2] = {nullptr, nullptr};   // two buffers of C slots: s(k C + j)
     void* lam = nullptr;         // 2 slots
     double* nu_acc = nullptr;    // n
     double* gthw = nullptr;      // n
@@ -51,8 +53,8 @@ struct AdjointState {
     static constexpr int kUnit = 50;
     hipGraphExec_t fwd[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipGraph_t fwd_def[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-    hipGraphExec_t bwd[2] = {nullptr, nullptr};
-    hipGraph_t bwd_def[2] = {nullptr, nullptr};
+    hipGraphExec_t bwd[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraph_t bwd_def[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
 
 void free_adjoint(AdjointState* a)
@@ -63,10 +65,13 @@ void free_adjoint(AdjointState* a)
             if (a->fwd[p][v]) (void)hipGraphExecDestroy(a->fwd[p][v]);
             if (a->fwd_def[p][v]) (void)hipGraphDestroy(a->fwd_def[p][v]);
         }
-        if (a->bwd[p]) (void)hipGraphExecDestroy(a->bwd[p]);
-        if (a->bwd_def[p]) (void)hipGraphDestroy(a->bwd_def[p]);
+        for (int b = 0; b < 2; ++b) {
+            if (a->bwd[p][b]) (void)hipGraphExecDestroy(a->bwd[p][b]);
+            if (a->bwd_def[p][b]) (void)hipGraphDestroy(a->bwd_def[p][b]);
+        }
     }
-    void* ptrs[] = {a->ckpt, a->seg, a->lam, a->nu_acc, a->gthw, a->grad0, a->sum, a->n0, a->n0_table};
+    void* ptrs[] = {a->ckpt, a->seg[0], a->seg[1], a->lam, a->nu_acc, a->gthw, a->grad0, a->sum,
+                    a->n0, a->n0_table};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete a;
@@ -157,20 +162,10 @@ int run_fwd(dmrt_cavity* h, AdjointState* a, long count, bool nu)
     return DMRT_OK;
 }
 
-// Backward work of one segment of `len` states starting at seg slot 0:
-// recompute slots 1..len-1, then adjoint steps j = len..1.
 template <typename real>
-int enqueue_bwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, long len, int lam_from)
+AdjArgs<real> adj_args(const dmrt_cavity* h, const AdjointState* a)
 {
-    const size_t se = a->slot_elems;
-    const int P = h->plane;
-    for (long j = 1; j < len; ++j) {
-        real* src = slot<real>(a->seg, se, j - 1);
-        real* dst = slot<real>(a->seg, se, j);
-        int rc = launch_fwd<real>(h, a, s, src, src + 9 * (size_t)P, dst, dst + 9 * (size_t)P, false);
-        if (rc) return rc;
-    }
-    const double c = a->K > 0 ? h->d.H / (3.0 * (h->p.theta_hot - h->p.theta_cold) * h->n * a->K) : 0.0;
+    const double c = h->d.H / (3.0 * (h->p.theta_hot - h->p.theta_cold) * h->n * a->K);
     AdjArgs<real> A;
     A.thw = static_cast<const real*>(h->thw_real);
     A.gthw = a->gthw;
@@ -179,22 +174,62 @@ int enqueue_bwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, long len, int la
     A.seed0 = real(-9.0 * c);
     A.seed1 = real(c);
     A.cabb = (4.0 + h->d.a) / 10.0;
-    A.n = h->n; A.pitch = h->pitch; A.plane = P;
+    A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
     A.tiles_x = (h->n + h->block_x - 1) / h->block_x;
     A.tiles = A.tiles_x * ((h->n + h->block_y - 1) / h->block_y);
     A.c = make_coef<real>(h->p, h->d);
+    return A;
+}
+
+// Forward recompute of slots [r0, r1) of segment buffer `b` (slot r from r - 1).
+template <typename real>
+int enqueue_recompute(dmrt_cavity* h, AdjointState* a, hipStream_t s, int b, long r0, long r1)
+{
+    const size_t se = a->slot_elems, P = h->plane;
+    for (long r = r0; r < r1; ++r) {
+        real* src = slot<real>(a->seg[b], se, r - 1);
+        real* dst = slot<real>(a->seg[b], se, r);
+        int rc = launch_fwd<real>(h, a, s, src, src + 9 * P, dst, dst + 9 * P, false);
+        if (rc) return rc;
+    }
+    return DMRT_OK;
+}
+
+// Backward of one segment held in buffer `b` (len states), pipelined with
+// the recompute of the next-older segment into buffer b ^ 1 (rec_len
+// states, slot 0 already filled; 0 when there is none): launch t runs the
+// adjoint of the segment's step len - t and the forward recompute of slot
+// t + 1 of the other buffer.
+template <typename real>
+int enqueue_segment(dmrt_cavity* h, AdjointState* a, hipStream_t s, int b, long len, long rec_len,
+                    int lam_from)
+{
+    const size_t se = a->slot_elems, P = h->plane;
+    AdjArgs<real> A = adj_args<real>(h, a);
     int l = lam_from;
-    for (long j = len; j >= 1; --j) {
-        real* st = slot<real>(a->seg, se, j - 1);
+    for (long t = 0; t < len; ++t) {
+        const long j = len - t;
+        real* st = slot<real>(a->seg[b], se, j - 1);
         A.fs = st;
-        A.gs = st + 9 * (size_t)P;
+        A.gs = st + 9 * P;
         A.lin = slot<real>(a->lam, se, l);
         A.lout = slot<real>(a->lam, se, l ^ 1);
         A.j = (int)j;
-        hipLaunchKernelGGL((adj_step_kernel<real>), dim3(A.tiles), dim3(h->block_x, h->block_y), 0, s, A);
+        const long r = t + 1;
+        if (r < rec_len) {
+            real* src = slot<real>(a->seg[b ^ 1], se, r - 1);
+            real* dst = slot<real>(a->seg[b ^ 1], se, r);
+            const StepArgs<real> R = step_args<real>(h, src, src + 9 * P, dst, dst + 9 * P);
+            hipLaunchKernelGGL((adj_fused_kernel<real>), dim3(A.tiles + R.tiles),
+                               dim3(h->block_x, h->block_y), 0, s, A, R);
+        } else {
+            hipLaunchKernelGGL((adj_step_kernel<real>), dim3(A.tiles), dim3(h->block_x, h->block_y), 0,
+                               s, A);
+        }
         HIPCHK(hipGetLastError());
         l ^= 1;
     }
+    if (rec_len - 1 > len) return enqueue_recompute<real>(h, a, s, b ^ 1, len + 1, rec_len);
     return DMRT_OK;
 }
 
@@ -212,7 +247,8 @@ int ensure_state(dmrt_cavity* h, long N, long K, long C)
     const size_t sb = a->slot_elems * h->esz;
     const size_t nn = (size_t)h->n * h->n;
     HIPCHK(hipMalloc(&a->ckpt, sb * nseg));
-    HIPCHK(hipMalloc(&a->seg, sb * C));
+    HIPCHK(hipMalloc(&a->seg[0], sb * C));
+    HIPCHK(hipMalloc(&a->seg[1], sb * C));
     HIPCHK(hipMalloc(&a->lam, sb * 2));
     HIPCHK(hipMemsetAsync(a->lam, 0, sb * 2, h->stream));
     HIPCHK(hipMalloc(&a->nu_acc, h->n * sizeof(double)));
@@ -281,28 +317,41 @@ int backward_t(dmrt_cavity* h, double* gw, double* g0)
                        h->pitch, h->plane, real(-9.0 * c), real(c));
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemsetAsync(a->gthw, 0, h->n * sizeof(double), h->stream));
-    int l = 0;
-    for (int k = a->nseg - 1; k >= 0; --k) {
-        const long len = std::min<long>(a->C, a->N - (long)k * a->C);
-        HIPCHK(hipMemcpyAsync(a->seg, static_cast<char*>(a->ckpt) + (size_t)k * se * esz, se * esz,
+    auto seg_len = [&](int k) { return std::min<long>(a->C, a->N - (long)k * a->C); };
+    auto load_ckpt = [&](int k, int b) -> int {
+        HIPCHK(hipMemcpyAsync(a->seg[b], static_cast<char*>(a->ckpt) + (size_t)k * se * esz, se * esz,
                               hipMemcpyDeviceToDevice, h->stream));
+        return DMRT_OK;
+    };
+    // prologue: the newest segment is recomputed on its own
+    const int last = a->nseg - 1;
+    int rc;
+    if ((rc = load_ckpt(last, last & 1))) return rc;
+    if ((rc = enqueue_recompute<real>(h, a, h->stream, last & 1, 1, seg_len(last)))) return rc;
+    int l = 0;
+    for (int k = last; k >= 0; --k) {
+        const int b = k & 1;
+        const long len = seg_len(k);
+        const long rec_len = k >= 1 ? seg_len(k - 1) : 0;
+        if (k >= 1 && (rc = load_ckpt(k - 1, b ^ 1))) return rc;
         HIPCHK(hipMemcpyAsync(a->n0, a->n0_table + k, sizeof(int), hipMemcpyDeviceToDevice, h->stream));
-        if (len == a->C && a->C >= 2) {
-            if (!a->bwd[l]) {
+        if (len == a->C && rec_len == a->C && a->C >= 2) {
+            // every full segment with a full predecessor has the same launch
+            // sequence: replay one captured graph per (lambda parity, buffer)
+            if (!a->bwd[l][b]) {
                 HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-                int rc = enqueue_bwd<real>(h, a, h->cap_stream, len, l);
+                rc = enqueue_segment<real>(h, a, h->cap_stream, b, len, rec_len, l);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
                 if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
                 if (e != hipSuccess) return record_hip(e, "hipStreamEndCapture");
-                e = hipGraphInstantiate(&a->bwd[l], g, nullptr, nullptr, 0);
+                e = hipGraphInstantiate(&a->bwd[l][b], g, nullptr, nullptr, 0);
                 if (e != hipSuccess) { (void)hipGraphDestroy(g); return record_hip(e, "hipGraphInstantiate"); }
-                a->bwd_def[l] = g;
+                a->bwd_def[l][b] = g;
             }
-            HIPCHK(hipGraphLaunch(a->bwd[l], h->stream));
+            HIPCHK(hipGraphLaunch(a->bwd[l][b], h->stream));
         } else {
-            int rc = enqueue_bwd<real>(h, a, h->stream, len, l);
-            if (rc) return rc;
+            if ((rc = enqueue_segment<real>(h, a, h->stream, b, len, rec_len, l))) return rc;
         }
         if (len & 1) l ^= 1;
     }

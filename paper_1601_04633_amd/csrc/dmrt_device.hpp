@@ -367,10 +367,8 @@ struct AdjArgs {
 // transposed streaming is a push: every lambda(n-1) entry has exactly one
 // writer.  The anti-bounce-back constant's derivative feeds dJ/dtheta_w.
 template <typename real>
-__global__ void __launch_bounds__(1024) adj_step_kernel(AdjArgs<real> A)
+__device__ __forceinline__ void adj_tile(const AdjArgs<real>& A, int tile)
 {
-    const int tile = blockIdx.x;
-    if (tile >= A.tiles) return;
     const int ty = tile / A.tiles_x;
     const int tx = tile - ty * A.tiles_x;
     const int x = tx * blockDim.x + threadIdx.x;
@@ -421,6 +419,35 @@ __global__ void __launch_bounds__(1024) adj_step_kernel(AdjArgs<real> A)
     else lg_o[1 * P + k] = sx - lg[3];                          // Eq. 45, right wall
     if (hym) lg_o[2 * P + k - pitch] = lg[2] + sx; else lg_o[4 * P + k] = lg[2] + sx;
     if (hyp) lg_o[4 * P + k + pitch] = lg[4] + sx; else lg_o[2 * P + k] = lg[4] + sx;
+}
+
+template <typename real>
+__global__ void __launch_bounds__(1024) adj_step_kernel(AdjArgs<real> A)
+{
+    if ((int)blockIdx.x >= A.tiles) return;
+    adj_tile<real>(A, blockIdx.x);
+}
+
+// One adjoint step of the current segment and, in the same launch, one
+// forward step recomputing the next (older) segment: the two touch disjoint
+// buffers.  Workgroups [0, A.tiles) take adjoint tiles, the rest take
+// forward tiles of R.
+template <typename real>
+__global__ void __launch_bounds__(1024) adj_fused_kernel(AdjArgs<real> A, StepArgs<real> R)
+{
+    const int b = blockIdx.x;
+    if (b < A.tiles) {
+        adj_tile<real>(A, b);
+        return;
+    }
+    const int tile = b - A.tiles;
+    if (tile >= R.tiles) return;
+    const int ty = tile / R.tiles_x;
+    const int tx = tile - ty * R.tiles_x;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y = ty * blockDim.y + threadIdx.y;
+    if (x >= R.n || y >= R.n) return;
+    node_update<real, BC_CAVITY>(R.fin, R.gin, R.fout, R.gout, R.thw, R.n, R.pitch, R.plane, x, y, R.c);
 }
 
 // lambda(N) = dJ/ds(N): zero except the temperature seed next to the hot wall.

@@ -20,7 +20,8 @@ import re
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdmrt.so")
+# DMRT_LIB: path of another build of the same library (e.g. a variant under test)
+LIB_PATH = os.environ.get("DMRT_LIB") or os.path.join(_HERE, "libdmrt.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "dmrt.h")
 
 if not os.path.exists(LIB_PATH):
