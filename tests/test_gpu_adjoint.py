@@ -62,13 +62,16 @@ def test_many_steps_against_reference(n, N, K, C):
     assert rel(g0, r0) <= 1e-10, rel(g0, r0)
 
 
-def test_checkpoint_interval_does_not_change_gradients():
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_checkpoint_interval_does_not_change_gradients(precision):
+    """The recompute reproduces the forward bitwise, so the gradients do not
+    depend on the checkpoint interval (C = 1 recomputes nothing)."""
     n, N, K = 24, 300, 100
     tw = inputs.hot_wall_profile(n, 25)
     t0 = inputs.theta_noise(n, 26, amp=1e-2)
     ref = None
     for C in (1, 7, 50, 300):
-        out = _gpu_grad(n, 1e4, 0.01, tw, t0, N, K, C)
+        out = _gpu_grad(n, 1e4, 0.01, tw, t0, N, K, C, precision)
         if ref is None:
             ref = out
         else:
