@@ -236,7 +236,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--single-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a plain 256 MiB device copy (counter calibration)")
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -285,15 +285,17 @@ def main():
     }
 
     if args.calib_copy:
-        # a plain copy of known size: 256 MiB read + 256 MiB written per launch,
-        # so HBM byte counters can be scaled against the true traffic
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        # a plain copy of known size, 1 GiB read + 1 GiB written per launch
+        # (larger than the last-level cache), repeated, so that HBM byte
+        # counters can be scaled against the true traffic
+        src = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(5):
+        for _ in range(8):
             dst.copy_(src)
         torch.cuda.synchronize()
         out["calib_copy_bytes_each_way"] = src.numel() * 4
-        log("calibration copy: 5 x 256 MiB")
+        del src, dst
+        log("calibration copy: 8 x 1 GiB")
 
     sections = set(args.sections.split(","))
     if args.no_extras:
