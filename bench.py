@@ -30,7 +30,15 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (D2Q9+D2Q5 node updates/s), % HBM roofline; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD published)
 WORDS_PER_NODE = 28            # 14 populations read + 14 written per node update
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json")
+TRAFFIC_FILES = {
+    "step_kernel<float, BC_CAVITY>": os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json"),
+    "step2_kernel<float, 6>": os.path.join(ROOT, "profiles", "step2_kernel_cavity_1024_fp32_traffic.json"),
+}
+# launch configuration timed by default (the autotuner's choice for this
+# workload on MI355X): two steps per launch through LDS, 64 x 6 tiles,
+# die-aware tile order, graphs of 64 steps
+DEFAULT_TEMPORAL = (2, 6)
+DEFAULT_LAUNCH = (256, 1, 1, 64)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_04633_amd", "csrc", f)
                   for f in ("dmrt_device.hpp",)]
 
@@ -47,21 +55,21 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_alg_per_launch):
+def measured_traffic(bytes_alg_per_launch, kernel):
     """HBM bytes per launch from the committed counter summary, or None when
     it is missing or was taken on a different kernel source."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[kernel]) as fh:
             t = json.load(fh)
-    except (OSError, ValueError):
+    except (OSError, ValueError, KeyError):
         return None
     if t.get("kernel_hash") != kernel_hash():
         return None
     return t.get("bytes_per_launch")
 
 
-def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601):
-    """Returns (ms total, MLUPS, avg ms per launch) for `steps` steps timed
+def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601, temporal=None):
+    """Returns (ms total, MLUPS, avg ms per step, Nu) for `steps` steps timed
     with HIP events on the cavity's own stream."""
     import torch
     from paper_1601_04633_amd import inputs
@@ -70,6 +78,8 @@ def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601):
     c = Cavity(n=n, Ra=Ra, Pr=Pr, precision=precision, stream=stream.cuda_stream)
     if launch:
         c.set_launch(*launch)
+    if temporal:
+        c.set_temporal(*temporal)
     c.set_theta(inputs.theta_noise(n, seed))
     c.step(warmup)
     c.sync()
@@ -131,8 +141,7 @@ def bench_batch(steps, single_steps, count=64, seed=4633, tune=True):
         if m["n"] not in tuned:
             tuned[m["n"]] = autotune.tune_cavity(c, stream_ptr=stream.cuda_stream, use_cache=False)[0]
         else:
-            best = tuned[m["n"]]
-            c.set_launch(best["block"][0], best["block"][1], best["xcd_remap"], 64)
+            autotune.apply_cavity(c, tuned[m["n"]])
         c.step(128)
         c.sync()
         t0.record(stream)
@@ -148,7 +157,8 @@ def bench_batch(steps, single_steps, count=64, seed=4633, tune=True):
             "batch_over_one_by_one": round(batch_mlups / single_mlups, 3),
             "batch_hbm_frac": round(batch_mlups * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4),
             "schedule": {k: list(v) if isinstance(v, tuple) else v for k, v in cfg.items()} if cfg else None,
-            "single_launch_by_side": {str(k): {"block": list(v["block"]), "xcd_remap": v["xcd_remap"]}
+            "single_launch_by_side": {str(k): {"block": list(v["block"]), "xcd_remap": v["xcd_remap"],
+                                               "steps_per_launch_rows": list(v["temporal"])}
                                       for k, v in tuned.items()},
             "dead_members": int((status != 0).sum()),
             "nu_hot_wall_mean": float(nu[np.isfinite(nu)].mean())}
@@ -160,7 +170,7 @@ def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp3
     checkpointed forward that also accumulates J, and of the backward
     (segment recompute + adjoint kernel)."""
     import torch
-    from paper_1601_04633_amd import inputs
+    from paper_1601_04633_amd import autotune, inputs
     from paper_1601_04633_amd.dmrt import Cavity
     stream = torch.cuda.Stream()
     c = Cavity(n=n, Ra=Ra, Pr=Pr, precision=precision, stream=stream.cuda_stream)
@@ -179,6 +189,9 @@ def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp3
         e1.synchronize()
         return out, e0.elapsed_time(e1) * 1e-3
 
+    # the forward reference is the fastest plain stepping of this cavity
+    best, _, _ = autotune.tune_cavity(c, stream_ptr=stream.cuda_stream, use_cache=False)
+    c.set_theta(t0)
     c.step(1000)                                  # warm-up, graphs
     c.sync()
     _, t_plain = timed(lambda: c.step(N))
@@ -189,6 +202,8 @@ def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp3
     c.close()
     return {"workload": f"{n}x{n} cavity, Ra={Ra:g}, Pr={Pr:g}, {precision.upper()}, {N} steps, "
                         f"J = mean hot-wall Nu over the last {K}, checkpoint every {C}",
+            "forward_launch": {"block": list(best["block"]), "xcd_remap": best["xcd_remap"],
+                               "steps_per_launch_rows": list(best["temporal"])},
             "forward_us_per_step": round(t_plain / N * 1e6, 3),
             "checkpointed_forward_us_per_step": round(t_fwd / N * 1e6, 3),
             "backward_us_per_step": round(t_bwd / N * 1e6, 3),
@@ -231,6 +246,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,xcd_remap,graph_steps")
+    ap.add_argument("--temporal", default="", help="steps_per_launch,tile_rows (default 2,6)")
     ap.add_argument("--sections", default="main,extras,batch,adjoint,cpu",
                     help="comma list of main, extras, batch, adjoint, cpu")
     ap.add_argument("--batch-steps", type=int, default=5000)
@@ -252,13 +268,27 @@ def main():
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
 
     n, Ra, Pr, prec = args.n, args.Ra, args.Pr, args.precision
-    log(f"main: {n}^2 Ra={Ra:g} Pr={Pr:g} {prec} steps={args.steps} warmup={args.warmup}")
-    ms, mlups, ms_launch, nu = time_cavity(n, Ra, Pr, prec, args.steps, args.warmup, launch)
+    temporal = tuple(int(v) for v in args.temporal.split(",")) if args.temporal else DEFAULT_TEMPORAL
+    if launch is None:
+        launch = DEFAULT_LAUNCH
+    log(f"main: {n}^2 Ra={Ra:g} Pr={Pr:g} {prec} steps={args.steps} warmup={args.warmup} "
+        f"launch={launch} steps/launch,rows={temporal}")
+    ms, mlups, ms_step, nu = time_cavity(n, Ra, Pr, prec, args.steps, args.warmup, launch,
+                                         temporal=temporal)
     esz = 8 if prec == "fp64" else 4
+    spl = temporal[0]                       # node updates per node per launch
+    ms_launch = ms_step * spl
+    # algorithmic bytes of one launch: every population read and written once
+    # per launch, i.e. 28 words per node per launch (14 words per node update
+    # for the two-step kernel, 28 for the single-step kernel)
     alg_bytes = WORDS_PER_NODE * esz * n * n
     achieved = alg_bytes / (ms_launch * 1e-3) / 1e9
-    traffic = measured_traffic(alg_bytes) if (n == 1024 and prec == "fp32" and not launch) else None
-    log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s, {ms_launch*1e3:.2f} us/launch, Nu {nu:.5f}")
+    single_equiv = WORDS_PER_NODE * esz * n * n * spl / (ms_launch * 1e-3) / 1e9
+    kname = (f"step2_kernel<{'float' if esz == 4 else 'double'}, {temporal[1]}>" if spl == 2
+             else f"step_kernel<{'float' if esz == 4 else 'double'}, BC_CAVITY>")
+    traffic = measured_traffic(alg_bytes, kname) if n == 1024 and prec == "fp32" else None
+    log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic per launch "
+        f"({single_equiv:.1f} GB/s single-step equivalent), {ms_launch*1e3:.2f} us/launch, Nu {nu:.5f}")
 
     out = {
         "metric": METRIC,
@@ -274,13 +304,20 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f32",
         "data": "synthetic: seeded uniform noise of amplitude 1e-4 on theta at rest (numpy PCG64, seed 1601)",
         "config": {"workload": f"differentially heated cavity {n}x{n}, Ra={Ra:g}, Pr={Pr:g}, "
-                               f"Ma=0.1, walls +-0.5, {prec.upper()} fused collide-stream step",
+                               f"Ma=0.1, walls +-0.5, {prec.upper()} fused collide-stream step, "
+                               f"{spl} step(s) per launch",
                    "global_batch": 1, "nodes": n * n, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "step_kernel<float, BC_CAVITY>",
-                     "bytes_per_node_update": WORDS_PER_NODE * esz},
+                     "kernel": kname,
+                     "node_updates_per_launch": spl * n * n,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "bytes_per_node_update": WORDS_PER_NODE * esz // spl,
+                     "single_step_equivalent_GBs": round(single_equiv, 1),
+                     "single_step_equivalent_frac": round(single_equiv / HBM_PEAK_GBS, 4)},
+        "launch": {"block": list(launch[:2]), "xcd_remap": launch[2], "graph_steps": launch[3],
+                   "steps_per_launch": spl, "tile_rows": temporal[1]},
         "nu_hot_wall": nu,
     }
 
@@ -306,13 +343,18 @@ def main():
     if "extras" in sections:
         extras = {}
         log("extra: fp64 same cavity")
-        _, m64, l64, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1000), 500)
-        extras["fp64_mlups"] = round(m64, 1)
-        extras["fp64_hbm_frac"] = round(224 * n * n / (l64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        _, m64, l64, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1000), 500, launch,
+                                     temporal=(2, 4))
+        extras["fp64_two_step_R4_mlups"] = round(m64, 1)
+        extras["fp64_hbm_frac"] = round(112 * n * n / (l64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        _, m1, l1, _ = time_cavity(n, Ra, Pr, prec, max(args.steps // 5, 2000), 500, launch,
+                                   temporal=(1, 10))
+        extras["fp32_single_step_mlups"] = round(m1, 1)
+        extras["fp32_single_step_hbm_frac"] = round(112 * n * n / (l1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         log("extra: 2048^2 fp32 control (state larger than the 256 MB last-level cache)")
-        _, m2k, l2k, _ = time_cavity(2048, Ra, Pr, "fp32", 5000, 500)
-        extras["fp32_2048_mlups"] = round(m2k, 1)
-        extras["fp32_2048_hbm_frac"] = round(112 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        _, m2k, l2k, _ = time_cavity(2048, Ra, Pr, "fp32", 5000, 500, launch, temporal=(2, 10))
+        extras["fp32_2048_two_step_R10_mlups"] = round(m2k, 1)
+        extras["fp32_2048_hbm_frac"] = round(56 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         out["extras"] = extras
     if "batch" in sections:
         log("batch: 64-cavity Ra x Pr sweep vs one by one")

@@ -206,6 +206,15 @@ int dmrt_load_state(dmrt_cavity *h, const void *host, size_t bytes);
 int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
                     int graph_steps);
 
+/* Steps per launch of dmrt_step: 1 (one fused kernel per step) or 2 (two
+ * steps per launch through LDS: each workgroup computes the intermediate
+ * step on its 64 x tile_rows footprint and keeps it in LDS; HBM traffic per
+ * node update drops from 28 to about 16 words).  tile_rows in {4, 6, 10,
+ * 16}; 2 is available for DMRT_BC_CAVITY only (EINVAL otherwise).  Results
+ * are identical to single steps; Nusselt samples are still taken after
+ * every stride-th step. */
+int dmrt_set_temporal(dmrt_cavity *h, int steps_per_launch, int tile_rows);
+
 /* Device pointers of the two ping-pong copies and the index (0/1) of the
  * copy holding the current state; for callers that manage memory. */
 int dmrt_buffers(dmrt_cavity *h, void **f, void **g, int *current);

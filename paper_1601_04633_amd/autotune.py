@@ -9,8 +9,8 @@ in a JSON file keyed by (device architecture, precision, member sizes).
 Batch schedule dimensions (dmrt_batch_set_schedule): tile shape, tile
 order, workgroups per launch, and cavity groups sized for the 256 MB
 last-level cache that run several steps before the next group.
-Single-cavity dimensions (dmrt_set_launch): tile shape and die-aware tile
-order.
+Single-cavity dimensions: steps per launch and tile rows
+(dmrt_set_temporal), tile shape and die-aware tile order (dmrt_set_launch).
 """
 from __future__ import annotations
 
@@ -34,10 +34,11 @@ BATCH_SPACE = {
 BATCH_DEFAULT = {"block": (64, 4), "order": 1, "grid_blocks": 0, "group": (0, 64)}
 
 CAVITY_SPACE = {
+    "temporal": [(2, 6), (2, 4), (2, 10), (2, 16), (1, 10)],
     "block": [(256, 1), (128, 2), (64, 4), (512, 1), (128, 1), (64, 1), (256, 2)],
     "xcd_remap": [1, 0],
 }
-CAVITY_DEFAULT = {"block": (256, 1), "xcd_remap": 1}
+CAVITY_DEFAULT = {"temporal": (2, 6), "block": (256, 1), "xcd_remap": 1}
 
 
 def _arch():
@@ -169,15 +170,21 @@ def tune_batch(batch, stream_ptr=None, min_steps=128, use_cache=True, verbose=Fa
 def tune_cavity(cavity, stream_ptr=None, steps=256, use_cache=True, verbose=False):
     """Pick the fastest single-cavity launch shape; leaves it applied."""
     key = f"cavity|{_arch()}|{'fp64' if cavity.params.precision == 1 else 'fp32'}|{cavity.n}"
+    if cavity.params.bc_mode != 0:
+        space = {k: v for k, v in CAVITY_SPACE.items() if k != "temporal"}
+        space["temporal"] = [(1, 10)]
+    else:
+        space = CAVITY_SPACE
     if use_cache:
         hit = _load_cache().get(key)
         if hit:
-            cavity.set_launch(hit["block"][0], hit["block"][1], hit["xcd_remap"], 64)
+            apply_cavity(cavity, {"temporal": tuple(hit["temporal"]), "block": tuple(hit["block"]),
+                                  "xcd_remap": hit["xcd_remap"]})
             return hit, hit.get("sec_per_step"), []
     start, stop = _timer(stream_ptr)
 
     def measure(cfg):
-        cavity.set_launch(cfg["block"][0], cfg["block"][1], cfg["xcd_remap"], 64)
+        apply_cavity(cavity, cfg)
         cavity.step(128)
         cavity.sync()
         start()
@@ -187,8 +194,16 @@ def tune_cavity(cavity, stream_ptr=None, steps=256, use_cache=True, verbose=Fals
             print(f"[autotune] cavity n={cavity.n} {cfg} {t * 1e6:.2f} us/step", flush=True)
         return t
 
-    best, best_t, trials = _coordinate_search(CAVITY_SPACE, CAVITY_DEFAULT, measure, sweeps=1)
-    cavity.set_launch(best["block"][0], best["block"][1], best["xcd_remap"], 64)
-    _store_cache(key, {"block": list(best["block"]), "xcd_remap": best["xcd_remap"],
-                       "sec_per_step": best_t})
+    default = dict(CAVITY_DEFAULT)
+    default["temporal"] = space["temporal"][0]
+    best, best_t, trials = _coordinate_search(space, default, measure, sweeps=1)
+    apply_cavity(cavity, best)
+    _store_cache(key, {"temporal": list(best["temporal"]), "block": list(best["block"]),
+                       "xcd_remap": best["xcd_remap"], "sec_per_step": best_t})
     return best, best_t, trials
+
+
+def apply_cavity(cavity, cfg):
+    """Applies a single-cavity launch configuration (see CAVITY_SPACE)."""
+    cavity.set_launch(cfg["block"][0], cfg["block"][1], cfg["xcd_remap"], 64)
+    cavity.set_temporal(cfg["temporal"][0], cfg["temporal"][1])

@@ -51,6 +51,7 @@ struct AdjointState {
     // graphs: forward units (plain / Nusselt-accumulating) by parity, and a
     // full backward segment by lambda parity
     static constexpr int kUnit = 50;
+    int fwd_flips[2][2] = {{0, 0}, {0, 0}};
     hipGraphExec_t fwd[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipGraph_t fwd_def[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipGraphExec_t bwd[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -119,17 +120,52 @@ real* cur_f(dmrt_cavity* h, int copy) { return static_cast<real*>(h->fbuf) + (si
 template <typename real>
 real* cur_g(dmrt_cavity* h, int copy) { return static_cast<real*>(h->gbuf) + (size_t)copy * 5 * h->plane; }
 
-// `count` forward steps on the cavity's ping-pong copies starting at `from`.
 template <typename real>
-int enqueue_fwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, int from, long count, bool nu)
+int launch_fwd2(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
+                real* gout)
 {
-    int c = from;
-    for (long i = 0; i < count; ++i) {
-        int rc = launch_fwd<real>(h, a, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),
+    StepArgs<real> A = step_args<real>(h, fin, gin, fout, gout);
+    const int R = h->t_rows;
+    A.tiles_x = (h->n + kT2Out - 1) / kT2Out;
+    A.tiles = A.tiles_x * ((h->n + R - 3) / (R - 2));
+    int nblocks = A.tiles;
+    if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
+    const dim3 grid(nblocks), block(kT2Width, R);
+    switch (R) {
+    case 4: hipLaunchKernelGGL((step2_kernel<real, 4>), grid, block, 0, s, A); break;
+    case 6: hipLaunchKernelGGL((step2_kernel<real, 6>), grid, block, 0, s, A); break;
+    case 10: hipLaunchKernelGGL((step2_kernel<real, 10>), grid, block, 0, s, A); break;
+    default: hipLaunchKernelGGL((step2_kernel<real, 16>), grid, block, 0, s, A); break;
+    }
+    HIPCHK(hipGetLastError());
+    return DMRT_OK;
+}
+
+// `count` forward steps on the cavity's ping-pong copies starting at `from`;
+// plain steps go two per launch when the handle's launch shape says so.
+// *flips receives the number of launches (copy changes).
+template <typename real>
+int enqueue_fwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, int from, long count, bool nu,
+                int* flips)
+{
+    int c = from, nf = 0;
+    long i = 0;
+    while (i < count) {
+        int rc;
+        if (!nu && h->temporal == 2 && i + 2 <= count) {
+            rc = launch_fwd2<real>(h, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),
+                                   cur_g<real>(h, c ^ 1));
+            i += 2;
+        } else {
+            rc = launch_fwd<real>(h, a, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),
                                   cur_g<real>(h, c ^ 1), nu);
+            i += 1;
+        }
         if (rc) return rc;
         c ^= 1;
+        ++nf;
     }
+    if (flips) *flips = nf;
     return DMRT_OK;
 }
 
@@ -139,25 +175,27 @@ int run_fwd(dmrt_cavity* h, AdjointState* a, long count, bool nu)
     const int U = AdjointState::kUnit;
     const int v = nu ? 1 : 0;
     while (count >= U) {
-        if (!a->fwd[h->cur][v]) {
+        const int p = h->cur;
+        if (!a->fwd[p][v]) {
             HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-            int rc = enqueue_fwd<real>(h, a, h->cap_stream, h->cur, U, nu);
+            int rc = enqueue_fwd<real>(h, a, h->cap_stream, p, U, nu, &a->fwd_flips[p][v]);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
             if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
             if (e != hipSuccess) return record_hip(e, "hipStreamEndCapture");
-            e = hipGraphInstantiate(&a->fwd[h->cur][v], g, nullptr, nullptr, 0);
+            e = hipGraphInstantiate(&a->fwd[p][v], g, nullptr, nullptr, 0);
             if (e != hipSuccess) { (void)hipGraphDestroy(g); return record_hip(e, "hipGraphInstantiate"); }
-            a->fwd_def[h->cur][v] = g;
+            a->fwd_def[p][v] = g;
         }
-        const long reps = count / U;
-        for (long r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(a->fwd[h->cur][v], h->stream));
-        count -= reps * U;              // U even: the copy index is unchanged
+        HIPCHK(hipGraphLaunch(a->fwd[p][v], h->stream));
+        h->cur ^= (a->fwd_flips[p][v] & 1);
+        count -= U;
     }
     if (count > 0) {
-        int rc = enqueue_fwd<real>(h, a, h->stream, h->cur, count, nu);
+        int flips = 0;
+        int rc = enqueue_fwd<real>(h, a, h->stream, h->cur, count, nu, &flips);
         if (rc) return rc;
-        if (count & 1) h->cur ^= 1;
+        if (flips & 1) h->cur ^= 1;
     }
     return DMRT_OK;
 }

@@ -509,6 +509,81 @@ static __global__ void __launch_bounds__(256) sum_kernel(const double* __restric
 }
 
 // ---------------------------------------------------------------------------
+// Two time steps per launch through LDS (temporal blocking), cavity walls.
+// ---------------------------------------------------------------------------
+// Workgroup of 64 x R threads; its footprint is 64 x R nodes starting one
+// node left of and below its output tile of 62 x (R - 2) nodes.  Phase 1:
+// every thread computes s(t+1) at its footprint node from s(t) in global
+// memory (the ordinary gather + collide) into LDS.  Phase 2: the inner
+// threads compute s(t+2) at the output nodes, gathering s(t+1) from LDS with
+// the same wall rules, and store it.  Each output node's neighbours lie in
+// the footprint, so the two steps equal two single-step launches exactly.
+// Global traffic per node update: (64 R / (62 (R - 2)) + 1) * 14 / 2 words
+// instead of 28.
+constexpr int kT2Width = 64;         // footprint width (one wavefront)
+constexpr int kT2Out = kT2Width - 2;
+
+template <typename real, int R>
+__device__ __forceinline__ real t2_lds(const real* lds, int q, int ly, int lx)
+{
+    return lds[(q * R + ly) * kT2Width + lx];
+}
+
+template <typename real, int R>
+__global__ void __launch_bounds__(kT2Width * R) step2_kernel(StepArgs<real> A)
+{
+    __shared__ real lds[14 * R * kT2Width];
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;                      // uniform per workgroup
+    const int tyt = tile / A.tiles_x;
+    const int txt = tile - tyt * A.tiles_x;
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int x = txt * kT2Out - 1 + lx;
+    const int y = tyt * (R - 2) - 1 + ly;
+    const int n = A.n;
+    const bool inside = x >= 0 && x < n && y >= 0 && y < n;
+    if (inside) {
+        real f[9], g[5];
+        gather<real, BC_CAVITY>(A.fin, A.gin, A.thw, n, A.pitch, A.plane, x, y, A.c, f, g);
+        real th, ux, uy;
+        collide<real>(f, g, A.c, th, ux, uy);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+    }
+    __syncthreads();
+    if (!inside || lx < 1 || lx > kT2Out || ly < 1 || ly > R - 2) return;
+
+    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
+    real f[9], g[5];
+    f[0] = t2_lds<real, R>(lds, 0, ly, lx);
+    f[1] = hxm ? t2_lds<real, R>(lds, 1, ly, lx - 1) : t2_lds<real, R>(lds, 3, ly, lx);
+    f[2] = hym ? t2_lds<real, R>(lds, 2, ly - 1, lx) : t2_lds<real, R>(lds, 4, ly, lx);
+    f[3] = hxp ? t2_lds<real, R>(lds, 3, ly, lx + 1) : t2_lds<real, R>(lds, 1, ly, lx);
+    f[4] = hyp ? t2_lds<real, R>(lds, 4, ly + 1, lx) : t2_lds<real, R>(lds, 2, ly, lx);
+    f[5] = (hxm && hym) ? t2_lds<real, R>(lds, 5, ly - 1, lx - 1) : t2_lds<real, R>(lds, 7, ly, lx);
+    f[6] = (hxp && hym) ? t2_lds<real, R>(lds, 6, ly - 1, lx + 1) : t2_lds<real, R>(lds, 8, ly, lx);
+    f[7] = (hxp && hyp) ? t2_lds<real, R>(lds, 7, ly + 1, lx + 1) : t2_lds<real, R>(lds, 5, ly, lx);
+    f[8] = (hxm && hyp) ? t2_lds<real, R>(lds, 8, ly + 1, lx - 1) : t2_lds<real, R>(lds, 6, ly, lx);
+    g[0] = t2_lds<real, R>(lds, 9, ly, lx);
+    g[2] = hym ? t2_lds<real, R>(lds, 11, ly - 1, lx) : t2_lds<real, R>(lds, 13, ly, lx);    // Eq. 44
+    g[4] = hyp ? t2_lds<real, R>(lds, 13, ly + 1, lx) : t2_lds<real, R>(lds, 11, ly, lx);
+    g[1] = hxm ? t2_lds<real, R>(lds, 10, ly, lx - 1)                                         // Eq. 45
+               : A.c.cabb * A.thw[y] - t2_lds<real, R>(lds, 12, ly, lx);
+    g[3] = hxp ? t2_lds<real, R>(lds, 12, ly, lx + 1) : A.c.cold - t2_lds<real, R>(lds, 10, ly, lx);
+
+    real th, ux, uy;
+    collide<real>(f, g, A.c, th, ux, uy);
+    const int k = y * A.pitch + x;
+    const int P = A.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) A.fout[i * P + k] = f[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) A.gout[i * P + k] = g[i];
+}
+
+// ---------------------------------------------------------------------------
 // Batched sweep: many independent cavities advanced by one launch
 // ---------------------------------------------------------------------------
 // Per-cavity parameter block, resident in device memory.

@@ -192,20 +192,63 @@ int launch_nusselt(dmrt_cavity* h, hipStream_t s, int copy, int wall, double* lo
                                     : launch_nusselt_t<float>(h, s, copy, wall, local, avg, to_ring);
 }
 
-// Enqueue `count` steps starting at copy `from` with Nu samples where due;
-// `base` is the step counter before the first of them.
-int enqueue_steps(dmrt_cavity* h, hipStream_t s, int from, long base, long count)
+template <typename real>
+int launch_step2_t(dmrt_cavity* h, hipStream_t s, int from)
 {
-    int c = from;
-    for (long i = 0; i < count; ++i) {
-        int rc = launch_step(h, s, c);
+    StepArgs<real> A;
+    A.fin = fptr<real>(h, from);
+    A.gin = gptr<real>(h, from);
+    A.fout = fptr<real>(h, from ^ 1);
+    A.gout = gptr<real>(h, from ^ 1);
+    A.thw = static_cast<const real*>(h->thw_real);
+    A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
+    const int R = h->t_rows;
+    A.tiles_x = (h->n + kT2Out - 1) / kT2Out;
+    A.tiles = A.tiles_x * ((h->n + R - 3) / (R - 2));
+    A.xcd_remap = h->xcd_remap;
+    A.c = make_coef<real>(h->p, h->d);
+    int nblocks = A.tiles;
+    if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
+    const dim3 grid(nblocks), block(kT2Width, R);
+    switch (R) {
+    case 4: hipLaunchKernelGGL((step2_kernel<real, 4>), grid, block, 0, s, A); break;
+    case 6: hipLaunchKernelGGL((step2_kernel<real, 6>), grid, block, 0, s, A); break;
+    case 10: hipLaunchKernelGGL((step2_kernel<real, 10>), grid, block, 0, s, A); break;
+    default: hipLaunchKernelGGL((step2_kernel<real, 16>), grid, block, 0, s, A); break;
+    }
+    HIPCHK(hipGetLastError());
+    return DMRT_OK;
+}
+
+// Enqueue `count` steps starting at copy `from` with Nu samples where due;
+// `base` is the step counter before the first of them.  Pairs of steps run
+// as one two-step launch when enabled and no sample falls between them.
+// *flips receives the number of launches (each moves the state to the
+// other copy).
+int enqueue_steps(dmrt_cavity* h, hipStream_t s, int from, long base, long count, int* flips)
+{
+    int c = from, nflip = 0;
+    const bool two = h->temporal == 2 && h->p.bc_mode == DMRT_BC_CAVITY;
+    long i = 0;
+    while (i < count) {
+        const bool due_mid = h->series_stride > 0 && (base + i + 1) % h->series_stride == 0;
+        int rc;
+        if (two && i + 2 <= count && !due_mid) {
+            rc = h->esz == sizeof(double) ? launch_step2_t<double>(h, s, c) : launch_step2_t<float>(h, s, c);
+            i += 2;
+        } else {
+            rc = launch_step(h, s, c);
+            i += 1;
+        }
         if (rc) return rc;
         c ^= 1;
-        if (h->series_stride > 0 && (base + i + 1) % h->series_stride == 0) {
+        ++nflip;
+        if (h->series_stride > 0 && (base + i) % h->series_stride == 0) {
             rc = launch_nusselt(h, s, c, 0, nullptr, nullptr, true);
             if (rc) return rc;
         }
     }
+    if (flips) *flips = nflip;
     return DMRT_OK;
 }
 
@@ -227,7 +270,7 @@ int graph_unit(const dmrt_cavity* h)
 int build_graph(dmrt_cavity* h, int parity, int unit)
 {
     HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_steps(h, h->cap_stream, parity, 0, unit);
+    int rc = enqueue_steps(h, h->cap_stream, parity, 0, unit, &h->graph_flips[parity]);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -465,9 +508,18 @@ int dmrt_step(dmrt_cavity* h, long nsteps)
                 int rc = build_graph(h, h->cur, unit);
                 if (rc) return rc;
             }
+            // replay one unit at a time: a unit may move the state to the
+            // other copy (odd number of launches), whose graph then follows
             const long reps = left / unit;
-            for (long r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(h->graph[h->cur], h->stream));
-            h->step += reps * unit;      // unit is even: cur is unchanged
+            for (long r = 0; r < reps; ++r) {
+                if (!h->graph[h->cur]) {
+                    int rc = build_graph(h, h->cur, unit);
+                    if (rc) return rc;
+                }
+                HIPCHK(hipGraphLaunch(h->graph[h->cur], h->stream));
+                h->cur ^= (h->graph_flips[h->cur] & 1);
+            }
+            h->step += reps * unit;
             left -= reps * unit;
         } else {
             long chunk = left;
@@ -475,10 +527,11 @@ int dmrt_step(dmrt_cavity* h, long nsteps)
                 const long to_align = unit - (h->step % unit);
                 if (to_align < chunk) chunk = to_align;
             }
-            int rc = enqueue_steps(h, h->stream, h->cur, h->step, chunk);
+            int flips = 0;
+            int rc = enqueue_steps(h, h->stream, h->cur, h->step, chunk, &flips);
             if (rc) return rc;
             h->step += chunk;
-            if (chunk & 1) h->cur ^= 1;
+            if (flips & 1) h->cur ^= 1;
             left -= chunk;
         }
     }
@@ -702,6 +755,21 @@ int dmrt_set_launch(dmrt_cavity* h, int block_x, int block_y, int xcd_remap, int
     h->block_y = block_y;
     h->xcd_remap = xcd_remap;
     h->graph_steps = graph_steps;
+    return DMRT_OK;
+}
+
+int dmrt_set_temporal(dmrt_cavity* h, int steps_per_launch, int tile_rows)
+{
+    if (!h) return DMRT_EINVAL;
+    if (steps_per_launch != 1 && steps_per_launch != 2) return DMRT_EINVAL;
+    if (tile_rows != 4 && tile_rows != 6 && tile_rows != 10 && tile_rows != 16) return DMRT_EINVAL;
+    if (steps_per_launch == 2 && h->p.bc_mode != DMRT_BC_CAVITY) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    if (h->adj) { free_adjoint(h->adj); h->adj = nullptr; }   // its graphs bake the mode
+    h->temporal = steps_per_launch;
+    h->t_rows = tile_rows;
     return DMRT_OK;
 }
 

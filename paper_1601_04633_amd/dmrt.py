@@ -94,6 +94,7 @@ _SIGS = {
     "dmrt_save_state": [_vp, _vp, _c_size],
     "dmrt_load_state": [_vp, _vp, _c_size],
     "dmrt_set_launch": [_vp, _c_int, _c_int, _c_int, _c_int],
+    "dmrt_set_temporal": [_vp, _c_int, _c_int],
     "dmrt_buffers": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_c_int)],
     "dmrt_destroy": [_vp],
     "dmrt_adjoint_forward": [_vp, _c_long, _c_long, _c_long, _dp],
@@ -331,6 +332,9 @@ class Cavity:
 
     def adjoint_release(self):
         check(dmrt_adjoint_release(self._h), "dmrt_adjoint_release")
+
+    def set_temporal(self, steps_per_launch=2, tile_rows=10):
+        check(dmrt_set_temporal(self._h, steps_per_launch, tile_rows), "dmrt_set_temporal")
 
     def buffers(self):
         f, g, c = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int(0)

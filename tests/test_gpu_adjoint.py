@@ -158,3 +158,22 @@ def test_autograd_function():
     assert float(J) == Jd
     assert np.array_equal(tw.grad.numpy(), 2.0 * gw)
     assert np.array_equal(t0.grad.numpy(), 2.0 * g0)
+
+
+def test_two_step_forward_does_not_change_gradients():
+    """The checkpointed forward may take two steps per launch; the gradients
+    are bitwise those of single-step launches."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    n, N, K, C = 48, 400, 150, 64
+    tw = inputs.hot_wall_profile(n, 29)
+    t0 = inputs.theta_noise(n, 30, amp=1e-2)
+    out = []
+    for temporal in ((1, 10), (2, 6), (2, 16)):
+        c = Cavity(n=n, Ra=1e4, Pr=0.01, precision="fp32")
+        c.set_temporal(*temporal)
+        c.set_hot_wall(tw)
+        c.set_theta(t0)
+        out.append(c.adjoint_nu(N, K, C))
+    for o in out[1:]:
+        assert o[0] == out[0][0]
+        assert np.array_equal(o[1], out[0][1]) and np.array_equal(o[2], out[0][2])
