@@ -292,6 +292,11 @@ int dmrt_batch_set_hot_wall(dmrt_batch *b, int index, const double *theta_w);
 int dmrt_batch_set_schedule(dmrt_batch *b, int block_x, int block_y, int order, int grid_blocks,
                             size_t group_bytes, int group_steps);
 
+/* Steps per launch of dmrt_batch_step for every member: 1, or 2 through LDS
+ * as dmrt_set_temporal (tile_rows in {4, 6, 10, 16}); with 2, each group
+ * advances its group_steps in pairs.  Results do not depend on it. */
+int dmrt_batch_set_temporal(dmrt_batch *b, int steps_per_launch, int tile_rows);
+
 /* Advance every live member nsteps >= 0 steps.  Enqueued only. */
 int dmrt_batch_step(dmrt_batch *b, long nsteps);
 int dmrt_batch_sync(dmrt_batch *b);

@@ -25,13 +25,15 @@ CACHE_PATH = os.environ.get("DMRT_AUTOTUNE_CACHE",
 MB = 1 << 20
 
 BATCH_SPACE = {
+    "temporal": [(2, 6), (2, 4), (2, 10), (2, 16), (1, 10)],
     "block": [(64, 4), (64, 2), (64, 8), (128, 2), (128, 4), (256, 1), (64, 1)],
     "order": [1, 0, 2],
     "grid_blocks": [0, 4096, 16384],
     "group": [(0, 64), (96 * MB, 8), (96 * MB, 32), (160 * MB, 16), (160 * MB, 64),
               (224 * MB, 32)],
 }
-BATCH_DEFAULT = {"block": (64, 4), "order": 1, "grid_blocks": 0, "group": (0, 64)}
+BATCH_DEFAULT = {"temporal": (2, 6), "block": (64, 4), "order": 1, "grid_blocks": 0,
+                 "group": (0, 64)}
 
 CAVITY_SPACE = {
     "temporal": [(2, 6), (2, 4), (2, 10), (2, 16), (1, 10)],
@@ -131,6 +133,7 @@ def apply_batch(batch, cfg):
     gb, gs = cfg["group"]
     batch.set_schedule(block_x=bx, block_y=by, order=cfg["order"],
                        grid_blocks=cfg["grid_blocks"], group_bytes=gb, group_steps=gs)
+    batch.set_temporal(*cfg.get("temporal", (1, 10)))
 
 
 def tune_batch(batch, stream_ptr=None, min_steps=128, use_cache=True, verbose=False):
@@ -140,8 +143,9 @@ def tune_batch(batch, stream_ptr=None, min_steps=128, use_cache=True, verbose=Fa
     if use_cache:
         hit = _load_cache().get(key)
         if hit:
-            cfg = {"block": tuple(hit["block"]), "order": hit["order"],
-                   "grid_blocks": hit["grid_blocks"], "group": tuple(hit["group"])}
+            cfg = {"temporal": tuple(hit.get("temporal", (1, 10))), "block": tuple(hit["block"]),
+                   "order": hit["order"], "grid_blocks": hit["grid_blocks"],
+                   "group": tuple(hit["group"])}
             apply_batch(batch, cfg)
             return cfg, hit.get("sec_per_step"), []
     start, stop = _timer(stream_ptr)
@@ -161,7 +165,8 @@ def tune_batch(batch, stream_ptr=None, min_steps=128, use_cache=True, verbose=Fa
 
     best, best_t, trials = _coordinate_search(BATCH_SPACE, BATCH_DEFAULT, measure)
     apply_batch(batch, best)
-    _store_cache(key, {"block": list(best["block"]), "order": best["order"],
+    _store_cache(key, {"temporal": list(best["temporal"]), "block": list(best["block"]),
+                       "order": best["order"],
                        "grid_blocks": best["grid_blocks"], "group": list(best["group"]),
                        "sec_per_step": best_t})
     return best, best_t, trials

@@ -50,6 +50,10 @@ struct dmrt_batch {
     TileRef* tiles = nullptr;
     std::vector<int> group_tile_begin;   // tile range of each group, plus end
     int ntiles = 0;
+    TileRef* tiles2 = nullptr;           // footprints of the two-step kernel
+    std::vector<int> group_tile2_begin;
+    int temporal = 1, t_rows = 10;       // steps per launch and footprint rows
+    int graph_flips[2] = {0, 0};
     double* nu = nullptr;
     int* flags = nullptr;
     double* scratch = nullptr;      // fields of one member
@@ -199,6 +203,23 @@ int build_tiles(dmrt_batch* b)
     HIPCHK(hipMalloc(&b->tiles, tiles.size() * sizeof(TileRef)));
     HIPCHK(hipMemcpyAsync(b->tiles, tiles.data(), tiles.size() * sizeof(TileRef),
                           hipMemcpyHostToDevice, b->stream));
+    // footprints of the two-step kernel, same groups and member order
+    std::vector<TileRef> fp;
+    b->group_tile2_begin.clear();
+    const int R = b->t_rows;
+    for (const auto& g : groups) {
+        b->group_tile2_begin.push_back((int)fp.size());
+        for (int i : g) {
+            const int n = b->p[i].n;
+            for (int y0 = 0; y0 < n; y0 += R - 2)
+                for (int x0 = 0; x0 < n; x0 += kT2Out) fp.push_back({i, x0 - 1, y0 - 1, 0});
+        }
+    }
+    b->group_tile2_begin.push_back((int)fp.size());
+    if (b->tiles2) { (void)hipFree(b->tiles2); b->tiles2 = nullptr; }
+    HIPCHK(hipMalloc(&b->tiles2, fp.size() * sizeof(TileRef)));
+    HIPCHK(hipMemcpyAsync(b->tiles2, fp.data(), fp.size() * sizeof(TileRef), hipMemcpyHostToDevice,
+                          b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     return DMRT_OK;
 }
@@ -221,25 +242,57 @@ int launch_range(dmrt_batch* b, hipStream_t s, int t0, int t1, int from)
                        : launch_range_t<float>(b, s, t0, t1, from);
 }
 
-// One round: each group in turn advances `steps` steps.
-int enqueue_round(dmrt_batch* b, hipStream_t s, int from, int steps)
+template <typename real>
+int launch_range2_t(dmrt_batch* b, hipStream_t s, int t0, int t1, int from)
+{
+    const int span = t1 - t0;
+    if (span <= 0) return DMRT_OK;
+    const int grid = b->grid_blocks > 0 ? std::min(span, b->grid_blocks) : span;
+    const CavityDev<real>* cv = static_cast<const CavityDev<real>*>(b->cavs);
+    const dim3 block(kT2Width, b->t_rows);
+    switch (b->t_rows) {
+    case 4: hipLaunchKernelGGL((batch_step2_kernel<real, 4>), dim3(grid), block, 0, s, cv, b->tiles2, t0, t1, from); break;
+    case 6: hipLaunchKernelGGL((batch_step2_kernel<real, 6>), dim3(grid), block, 0, s, cv, b->tiles2, t0, t1, from); break;
+    case 10: hipLaunchKernelGGL((batch_step2_kernel<real, 10>), dim3(grid), block, 0, s, cv, b->tiles2, t0, t1, from); break;
+    default: hipLaunchKernelGGL((batch_step2_kernel<real, 16>), dim3(grid), block, 0, s, cv, b->tiles2, t0, t1, from); break;
+    }
+    HIPCHK(hipGetLastError());
+    return DMRT_OK;
+}
+
+// One round: each group in turn advances `steps` steps (pairs of steps in
+// one launch when the two-step kernel is selected).  *flips receives the
+// number of launches per group (each moves the state to the other copy).
+int enqueue_round(dmrt_batch* b, hipStream_t s, int from, int steps, int* flips)
 {
     const int ng = (int)b->group_tile_begin.size() - 1;
+    int nf = 0;
     for (int g = 0; g < ng; ++g) {
-        int c = from;
-        for (int k = 0; k < steps; ++k) {
-            int rc = launch_range(b, s, b->group_tile_begin[g], b->group_tile_begin[g + 1], c);
+        int c = from, k = steps;
+        nf = 0;
+        while (k > 0) {
+            int rc;
+            if (b->temporal == 2 && k >= 2) {
+                rc = b->esz == 8 ? launch_range2_t<double>(b, s, b->group_tile2_begin[g], b->group_tile2_begin[g + 1], c)
+                                 : launch_range2_t<float>(b, s, b->group_tile2_begin[g], b->group_tile2_begin[g + 1], c);
+                k -= 2;
+            } else {
+                rc = launch_range(b, s, b->group_tile_begin[g], b->group_tile_begin[g + 1], c);
+                k -= 1;
+            }
             if (rc) return rc;
             c ^= 1;
+            ++nf;
         }
     }
+    if (flips) *flips = nf;
     return DMRT_OK;
 }
 
 int build_graph(dmrt_batch* b, int parity)
 {
     HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_round(b, b->cap_stream, parity, b->group_steps);
+    int rc = enqueue_round(b, b->cap_stream, parity, b->group_steps, &b->graph_flips[parity]);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -394,27 +447,43 @@ int dmrt_batch_set_schedule(dmrt_batch* b, int block_x, int block_y, int order, 
     return build_tiles(b);
 }
 
+int dmrt_batch_set_temporal(dmrt_batch* b, int steps_per_launch, int tile_rows)
+{
+    if (!b) return DMRT_EINVAL;
+    if (steps_per_launch != 1 && steps_per_launch != 2) return DMRT_EINVAL;
+    if (tile_rows != 4 && tile_rows != 6 && tile_rows != 10 && tile_rows != 16) return DMRT_EINVAL;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    b->temporal = steps_per_launch;
+    b->t_rows = tile_rows;
+    return build_tiles(b);
+}
+
 int dmrt_batch_step(dmrt_batch* b, long nsteps)
 {
     if (!b || nsteps < 0) return DMRT_EINVAL;
     const int G = b->group_steps;
     long left = nsteps;
-    if (G % 2 == 0 && left >= G) {
-        // whole rounds by graph replay; an even round returns to the same copy
-        if (!b->graph[b->cur]) {
-            int rc = build_graph(b, b->cur);
-            if (rc) return rc;
+    if (G >= 2) {
+        // whole rounds by graph replay (one graph per starting copy)
+        while (left >= G) {
+            const int p = b->cur;
+            if (!b->graph[p]) {
+                int rc = build_graph(b, p);
+                if (rc) return rc;
+            }
+            HIPCHK(hipGraphLaunch(b->graph[p], b->stream));
+            b->cur ^= (b->graph_flips[p] & 1);
+            b->step += G;
+            left -= G;
         }
-        const long reps = left / G;
-        for (long r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(b->graph[b->cur], b->stream));
-        b->step += reps * G;
-        left -= reps * G;
     }
     while (left > 0) {
         const int k = (int)std::min<long>(left, G);
-        int rc = enqueue_round(b, b->stream, b->cur, k);
+        int flips = 0;
+        int rc = enqueue_round(b, b->stream, b->cur, k, &flips);
         if (rc) return rc;
-        if (k & 1) b->cur ^= 1;
+        if (flips & 1) b->cur ^= 1;
         b->step += k;
         left -= k;
     }
@@ -545,7 +614,8 @@ int dmrt_batch_destroy(dmrt_batch* b)
     if (!b) return DMRT_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graphs(b);
-    void* ptrs[] = {b->arena, b->thw_real, b->thw_d, b->cavs, b->tiles, b->nu, b->flags, b->scratch};
+    void* ptrs[] = {b->arena, b->thw_real, b->thw_d, b->cavs, b->tiles, b->tiles2, b->nu, b->flags,
+                    b->scratch};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);

@@ -529,32 +529,29 @@ __device__ __forceinline__ real t2_lds(const real* lds, int q, int ly, int lx)
     return lds[(q * R + ly) * kT2Width + lx];
 }
 
+// Phase 1 of the two-step update: s(t+1) at footprint node (x, y) into LDS.
 template <typename real, int R>
-__global__ void __launch_bounds__(kT2Width * R) step2_kernel(StepArgs<real> A)
+__device__ __forceinline__ void t2_phase1(real* lds, const real* __restrict__ fi,
+                                          const real* __restrict__ gi, const real* __restrict__ thw,
+                                          int n, int pitch, int P, int x, int y, int lx, int ly,
+                                          const Coef<real>& c)
 {
-    __shared__ real lds[14 * R * kT2Width];
-    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
-    if (tile >= A.tiles) return;                      // uniform per workgroup
-    const int tyt = tile / A.tiles_x;
-    const int txt = tile - tyt * A.tiles_x;
-    const int lx = threadIdx.x, ly = threadIdx.y;
-    const int x = txt * kT2Out - 1 + lx;
-    const int y = tyt * (R - 2) - 1 + ly;
-    const int n = A.n;
-    const bool inside = x >= 0 && x < n && y >= 0 && y < n;
-    if (inside) {
-        real f[9], g[5];
-        gather<real, BC_CAVITY>(A.fin, A.gin, A.thw, n, A.pitch, A.plane, x, y, A.c, f, g);
-        real th, ux, uy;
-        collide<real>(f, g, A.c, th, ux, uy);
+    real f[9], g[5];
+    gather<real, BC_CAVITY>(fi, gi, thw, n, pitch, P, x, y, c, f, g);
+    real th, ux, uy;
+    collide<real>(f, g, c, th, ux, uy);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
+    for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
-    }
-    __syncthreads();
-    if (!inside || lx < 1 || lx > kT2Out || ly < 1 || ly > R - 2) return;
+    for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+}
 
+// Phase 2: s(t+2) at output node (x, y) from s(t+1) in LDS, stored to global.
+template <typename real, int R>
+__device__ __forceinline__ void t2_phase2(const real* lds, real* __restrict__ fo, real* __restrict__ go,
+                                          const real* __restrict__ thw, int n, int pitch, int P, int x,
+                                          int y, int lx, int ly, const Coef<real>& c)
+{
     const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
     real f[9], g[5];
     f[0] = t2_lds<real, R>(lds, 0, ly, lx);
@@ -570,17 +567,35 @@ __global__ void __launch_bounds__(kT2Width * R) step2_kernel(StepArgs<real> A)
     g[2] = hym ? t2_lds<real, R>(lds, 11, ly - 1, lx) : t2_lds<real, R>(lds, 13, ly, lx);    // Eq. 44
     g[4] = hyp ? t2_lds<real, R>(lds, 13, ly + 1, lx) : t2_lds<real, R>(lds, 11, ly, lx);
     g[1] = hxm ? t2_lds<real, R>(lds, 10, ly, lx - 1)                                         // Eq. 45
-               : A.c.cabb * A.thw[y] - t2_lds<real, R>(lds, 12, ly, lx);
-    g[3] = hxp ? t2_lds<real, R>(lds, 12, ly, lx + 1) : A.c.cold - t2_lds<real, R>(lds, 10, ly, lx);
+               : c.cabb * thw[y] - t2_lds<real, R>(lds, 12, ly, lx);
+    g[3] = hxp ? t2_lds<real, R>(lds, 12, ly, lx + 1) : c.cold - t2_lds<real, R>(lds, 10, ly, lx);
 
     real th, ux, uy;
-    collide<real>(f, g, A.c, th, ux, uy);
-    const int k = y * A.pitch + x;
-    const int P = A.plane;
+    collide<real>(f, g, c, th, ux, uy);
+    const int k = y * pitch + x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) A.fout[i * P + k] = f[i];
+    for (int i = 0; i < 9; ++i) fo[i * P + k] = f[i];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) A.gout[i * P + k] = g[i];
+    for (int i = 0; i < 5; ++i) go[i * P + k] = g[i];
+}
+
+template <typename real, int R>
+__global__ void __launch_bounds__(kT2Width * R) step2_kernel(StepArgs<real> A)
+{
+    __shared__ real lds[14 * R * kT2Width];
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;                      // uniform per workgroup
+    const int tyt = tile / A.tiles_x;
+    const int txt = tile - tyt * A.tiles_x;
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int x = txt * kT2Out - 1 + lx;
+    const int y = tyt * (R - 2) - 1 + ly;
+    const int n = A.n;
+    const bool inside = x >= 0 && x < n && y >= 0 && y < n;
+    if (inside) t2_phase1<real, R>(lds, A.fin, A.gin, A.thw, n, A.pitch, A.plane, x, y, lx, ly, A.c);
+    __syncthreads();
+    if (!inside || lx < 1 || lx > kT2Out || ly < 1 || ly > R - 2) return;
+    t2_phase2<real, R>(lds, A.fout, A.gout, A.thw, n, A.pitch, A.plane, x, y, lx, ly, A.c);
 }
 
 // ---------------------------------------------------------------------------
@@ -753,6 +768,31 @@ __global__ void __launch_bounds__(256) nusselt_kernel(
             ring[c % (unsigned long long)ring_cap] = avg;
             *ring_count = c + 1;
         }
+    }
+}
+
+// Two steps per launch for the batch: tiles are footprints (origin one node
+// left of and below the 62 x (R - 2) output tile) of one member each.
+template <typename real, int R>
+__global__ void __launch_bounds__(kT2Width * R) batch_step2_kernel(
+    const CavityDev<real>* __restrict__ cavs, const TileRef* __restrict__ tiles, int t_begin,
+    int t_end, int cur)
+{
+    __shared__ real lds[14 * R * kT2Width];
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    for (int t = t_begin + blockIdx.x; t < t_end; t += gridDim.x) {
+        const TileRef tr = tiles[t];
+        const CavityDev<real>& cv = cavs[tr.cav];
+        if (cv.dead) continue;                        // uniform per workgroup
+        const int x = tr.x0 + lx, y = tr.y0 + ly, n = cv.n;
+        const bool inside = x >= 0 && x < n && y >= 0 && y < n;
+        if (inside)
+            t2_phase1<real, R>(lds, cv.f[cur], cv.g[cur], cv.thw, n, cv.pitch, cv.plane, x, y, lx, ly, cv.c);
+        __syncthreads();
+        if (inside && lx >= 1 && lx <= kT2Out && ly >= 1 && ly <= R - 2)
+            t2_phase2<real, R>(lds, cv.f[cur ^ 1], cv.g[cur ^ 1], cv.thw, n, cv.pitch, cv.plane, x, y,
+                               lx, ly, cv.c);
+        __syncthreads();                              // the next tile reuses the LDS
     }
 }
 

@@ -105,6 +105,7 @@ _SIGS = {
     "dmrt_batch_set_theta": [_vp, _c_int, _dp],
     "dmrt_batch_set_hot_wall": [_vp, _c_int, _dp],
     "dmrt_batch_set_schedule": [_vp, _c_int, _c_int, _c_int, _c_int, _c_size, _c_int],
+    "dmrt_batch_set_temporal": [_vp, _c_int, _c_int],
     "dmrt_batch_step": [_vp, _c_long],
     "dmrt_batch_sync": [_vp],
     "dmrt_batch_get_step": [_vp, ctypes.POINTER(_c_long)],
@@ -398,6 +399,9 @@ class Batch:
                      group_steps=64):
         check(dmrt_batch_set_schedule(self._h, block_x, block_y, order, grid_blocks,
                                       int(group_bytes), group_steps), "dmrt_batch_set_schedule")
+
+    def set_temporal(self, steps_per_launch=2, tile_rows=10):
+        check(dmrt_batch_set_temporal(self._h, steps_per_launch, tile_rows), "dmrt_batch_set_temporal")
 
     def step(self, nsteps=1):
         check(dmrt_batch_step(self._h, int(nsteps)), "dmrt_batch_step")

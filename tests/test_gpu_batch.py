@@ -16,6 +16,10 @@ MEMBERS = [dict(n=64, Ra=1e4, Pr=0.01), dict(n=100, Ra=3e3, Pr=0.005),
 
 SCHEDULES = [
     dict(block_x=64, block_y=4, order=1, grid_blocks=0, group_bytes=0, group_steps=64),
+    dict(block_x=256, block_y=1, order=0, grid_blocks=0, group_bytes=0, group_steps=64, temporal=(2, 6)),
+    dict(block_x=64, block_y=4, order=2, grid_blocks=200, group_bytes=3 << 20, group_steps=7,
+         temporal=(2, 10)),
+    dict(block_x=128, block_y=2, order=1, grid_blocks=0, group_bytes=0, group_steps=32, temporal=(2, 16)),
     dict(block_x=256, block_y=1, order=0, grid_blocks=0, group_bytes=0, group_steps=10),
     dict(block_x=64, block_y=1, order=2, grid_blocks=300, group_bytes=0, group_steps=7),
     dict(block_x=128, block_y=2, order=1, grid_blocks=0, group_bytes=3 << 20, group_steps=16),
@@ -36,7 +40,10 @@ def test_batch_members_bitwise_equal_single(precision, sched):
     from paper_1601_04633_amd.dmrt import Batch
     print(f"[batch] {precision} schedule {SCHEDULES[sched]}", flush=True)
     b = Batch(MEMBERS, precision=precision)
-    b.set_schedule(**SCHEDULES[sched])
+    sc = dict(SCHEDULES[sched])
+    temporal = sc.pop("temporal", (1, 10))
+    b.set_schedule(**sc)
+    b.set_temporal(*temporal)
     th = [inputs.theta_noise(m["n"], 100 + i, amp=1e-3) for i, m in enumerate(MEMBERS)]
     for i, t in enumerate(th):
         b.set_theta(i, t)
