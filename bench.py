@@ -32,13 +32,16 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD published)
 WORDS_PER_NODE = 28            # 14 populations read + 14 written per node update
 TRAFFIC_FILES = {
     "step_kernel<float, BC_CAVITY>": os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json"),
-    "step2_kernel<float, 6>": os.path.join(ROOT, "profiles", "step2_kernel_cavity_1024_fp32_traffic.json"),
+    "stepk_kernel<float, 6, 2>": os.path.join(ROOT, "profiles", "step2_kernel_cavity_1024_fp32_traffic.json"),
+    "stepk_kernel<float, 10, 3>": os.path.join(ROOT, "profiles", "step3_kernel_cavity_1024_fp32_traffic.json"),
+    "stepk_kernel<float, 16, 3>": os.path.join(ROOT, "profiles", "step3r16_kernel_cavity_1024_fp32_traffic.json"),
+    "stepk_kernel<float, 16, 4>": os.path.join(ROOT, "profiles", "step4_kernel_cavity_1024_fp32_traffic.json"),
 }
-# launch configuration timed by default (the autotuner's choice for this
-# workload on MI355X): two steps per launch through LDS, 64 x 6 tiles,
-# die-aware tile order, graphs of 64 steps
-DEFAULT_TEMPORAL = (2, 6)
-DEFAULT_LAUNCH = (256, 1, 1, 64)
+# launch configuration timed by default (the fastest for this workload on
+# MI355X): three steps per launch through LDS, 64 x 16 footprints,
+# die-aware tile order, graphs of 60 steps
+DEFAULT_TEMPORAL = (3, 16)
+DEFAULT_LAUNCH = (256, 1, 1, 60)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_04633_amd", "csrc", f)
                   for f in ("dmrt_device.hpp",)]
 
@@ -246,7 +249,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,xcd_remap,graph_steps")
-    ap.add_argument("--temporal", default="", help="steps_per_launch,tile_rows (default 2,6)")
+    ap.add_argument("--temporal", default="", help="steps_per_launch,tile_rows (default 3,16)")
     ap.add_argument("--sections", default="main,extras,batch,adjoint,cpu",
                     help="comma list of main, extras, batch, adjoint, cpu")
     ap.add_argument("--batch-steps", type=int, default=5000)
@@ -284,7 +287,7 @@ def main():
     alg_bytes = WORDS_PER_NODE * esz * n * n
     achieved = alg_bytes / (ms_launch * 1e-3) / 1e9
     single_equiv = WORDS_PER_NODE * esz * n * n * spl / (ms_launch * 1e-3) / 1e9
-    kname = (f"step2_kernel<{'float' if esz == 4 else 'double'}, {temporal[1]}>" if spl == 2
+    kname = (f"stepk_kernel<{'float' if esz == 4 else 'double'}, {temporal[1]}, {spl}>" if spl >= 2
              else f"step_kernel<{'float' if esz == 4 else 'double'}, BC_CAVITY>")
     traffic = measured_traffic(alg_bytes, kname) if n == 1024 and prec == "fp32" else None
     log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic per launch "
@@ -343,18 +346,18 @@ def main():
     if "extras" in sections:
         extras = {}
         log("extra: fp64 same cavity")
-        _, m64, l64, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1000), 500, launch,
-                                     temporal=(2, 4))
-        extras["fp64_two_step_R4_mlups"] = round(m64, 1)
-        extras["fp64_hbm_frac"] = round(112 * n * n / (l64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        _, m64, l64, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1200), 600, launch,
+                                     temporal=(4, 16))
+        extras["fp64_four_step_R16_mlups"] = round(m64, 1)
+        extras["fp64_hbm_frac"] = round(224 / 4 * n * n / (l64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         _, m1, l1, _ = time_cavity(n, Ra, Pr, prec, max(args.steps // 5, 2000), 500, launch,
                                    temporal=(1, 10))
         extras["fp32_single_step_mlups"] = round(m1, 1)
         extras["fp32_single_step_hbm_frac"] = round(112 * n * n / (l1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         log("extra: 2048^2 fp32 control (state larger than the 256 MB last-level cache)")
-        _, m2k, l2k, _ = time_cavity(2048, Ra, Pr, "fp32", 5000, 500, launch, temporal=(2, 10))
-        extras["fp32_2048_two_step_R10_mlups"] = round(m2k, 1)
-        extras["fp32_2048_hbm_frac"] = round(56 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        _, m2k, l2k, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=(3, 16))
+        extras["fp32_2048_three_step_R16_mlups"] = round(m2k, 1)
+        extras["fp32_2048_hbm_frac"] = round(112 / 3 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         out["extras"] = extras
     if "batch" in sections:
         log("batch: 64-cavity Ra x Pr sweep vs one by one")

@@ -206,13 +206,15 @@ int dmrt_load_state(dmrt_cavity *h, const void *host, size_t bytes);
 int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
                     int graph_steps);
 
-/* Steps per launch of dmrt_step: 1 (one fused kernel per step) or 2 (two
- * steps per launch through LDS: each workgroup computes the intermediate
- * step on its 64 x tile_rows footprint and keeps it in LDS; HBM traffic per
- * node update drops from 28 to about 16 words).  tile_rows in {4, 6, 10,
- * 16}; 2 is available for DMRT_BC_CAVITY only (EINVAL otherwise).  Results
- * are identical to single steps; Nusselt samples are still taken after
- * every stride-th step. */
+/* Steps per launch K of dmrt_step: 1 (one fused kernel per step) or 2..4
+ * (K steps per launch through LDS: each workgroup computes the intermediate
+ * steps on its 64 x tile_rows footprint, shrinking by one node per step, and
+ * keeps them in LDS; every population is read and written once per launch,
+ * so HBM traffic per node update drops from 28 to about 28/K words plus
+ * halo).  tile_rows in {4, 6, 10, 16} for K <= 2, {6, 10, 16} for K = 3,
+ * {10, 16} for K = 4.  K >= 2 is available for DMRT_BC_CAVITY only (EINVAL
+ * otherwise).  Results are identical to single steps; Nusselt samples are
+ * still taken after every stride-th step. */
 int dmrt_set_temporal(dmrt_cavity *h, int steps_per_launch, int tile_rows);
 
 /* Device pointers of the two ping-pong copies and the index (0/1) of the
@@ -292,9 +294,10 @@ int dmrt_batch_set_hot_wall(dmrt_batch *b, int index, const double *theta_w);
 int dmrt_batch_set_schedule(dmrt_batch *b, int block_x, int block_y, int order, int grid_blocks,
                             size_t group_bytes, int group_steps);
 
-/* Steps per launch of dmrt_batch_step for every member: 1, or 2 through LDS
- * as dmrt_set_temporal (tile_rows in {4, 6, 10, 16}); with 2, each group
- * advances its group_steps in pairs.  Results do not depend on it. */
+/* Steps per launch K of dmrt_batch_step for every member: 1, or 2..4
+ * through LDS as dmrt_set_temporal (same tile_rows rules); each group
+ * advances its group_steps K at a time (the remainder one at a time).
+ * Results do not depend on it. */
 int dmrt_batch_set_temporal(dmrt_batch *b, int steps_per_launch, int tile_rows);
 
 /* Advance every live member nsteps >= 0 steps.  Enqueued only. */

@@ -120,29 +120,8 @@ real* cur_f(dmrt_cavity* h, int copy) { return static_cast<real*>(h->fbuf) + (si
 template <typename real>
 real* cur_g(dmrt_cavity* h, int copy) { return static_cast<real*>(h->gbuf) + (size_t)copy * 5 * h->plane; }
 
-template <typename real>
-int launch_fwd2(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
-                real* gout)
-{
-    StepArgs<real> A = step_args<real>(h, fin, gin, fout, gout);
-    const int R = h->t_rows;
-    A.tiles_x = (h->n + kT2Out - 1) / kT2Out;
-    A.tiles = A.tiles_x * ((h->n + R - 3) / (R - 2));
-    int nblocks = A.tiles;
-    if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
-    const dim3 grid(nblocks), block(kT2Width, R);
-    switch (R) {
-    case 4: hipLaunchKernelGGL((step2_kernel<real, 4>), grid, block, 0, s, A); break;
-    case 6: hipLaunchKernelGGL((step2_kernel<real, 6>), grid, block, 0, s, A); break;
-    case 10: hipLaunchKernelGGL((step2_kernel<real, 10>), grid, block, 0, s, A); break;
-    default: hipLaunchKernelGGL((step2_kernel<real, 16>), grid, block, 0, s, A); break;
-    }
-    HIPCHK(hipGetLastError());
-    return DMRT_OK;
-}
-
 // `count` forward steps on the cavity's ping-pong copies starting at `from`;
-// plain steps go two per launch when the handle's launch shape says so.
+// plain steps go K per launch when the handle's launch shape says so.
 // *flips receives the number of launches (copy changes).
 template <typename real>
 int enqueue_fwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, int from, long count, bool nu,
@@ -152,10 +131,10 @@ int enqueue_fwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, int from, long c
     long i = 0;
     while (i < count) {
         int rc;
-        if (!nu && h->temporal == 2 && i + 2 <= count) {
-            rc = launch_fwd2<real>(h, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),
-                                   cur_g<real>(h, c ^ 1));
-            i += 2;
+        if (!nu && h->temporal >= 2 && i + h->temporal <= count) {
+            rc = launch_stepk<real>(h, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),
+                                    cur_g<real>(h, c ^ 1));
+            i += h->temporal;
         } else {
             rc = launch_fwd<real>(h, a, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),
                                   cur_g<real>(h, c ^ 1), nu);

@@ -50,7 +50,7 @@ struct dmrt_batch {
     TileRef* tiles = nullptr;
     std::vector<int> group_tile_begin;   // tile range of each group, plus end
     int ntiles = 0;
-    TileRef* tiles2 = nullptr;           // footprints of the two-step kernel
+    TileRef* tiles2 = nullptr;           // footprints of the K-step kernel
     std::vector<int> group_tile2_begin;
     int temporal = 1, t_rows = 10;       // steps per launch and footprint rows
     int graph_flips[2] = {0, 0};
@@ -206,13 +206,14 @@ int build_tiles(dmrt_batch* b)
     // footprints of the two-step kernel, same groups and member order
     std::vector<TileRef> fp;
     b->group_tile2_begin.clear();
-    const int R = b->t_rows;
+    const int K = std::max(2, b->temporal), R = b->t_rows;
+    const int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
     for (const auto& g : groups) {
         b->group_tile2_begin.push_back((int)fp.size());
         for (int i : g) {
             const int n = b->p[i].n;
-            for (int y0 = 0; y0 < n; y0 += R - 2)
-                for (int x0 = 0; x0 < n; x0 += kT2Out) fp.push_back({i, x0 - 1, y0 - 1, 0});
+            for (int y0 = 0; y0 < n; y0 += HO)
+                for (int x0 = 0; x0 < n; x0 += W) fp.push_back({i, x0 - (K - 1), y0 - (K - 1), 0});
         }
     }
     b->group_tile2_begin.push_back((int)fp.size());
@@ -243,25 +244,30 @@ int launch_range(dmrt_batch* b, hipStream_t s, int t0, int t1, int from)
 }
 
 template <typename real>
-int launch_range2_t(dmrt_batch* b, hipStream_t s, int t0, int t1, int from)
+int launch_rangek_t(dmrt_batch* b, hipStream_t s, int t0, int t1, int from)
 {
     const int span = t1 - t0;
     if (span <= 0) return DMRT_OK;
     const int grid = b->grid_blocks > 0 ? std::min(span, b->grid_blocks) : span;
     const CavityDev<real>* cv = static_cast<const CavityDev<real>*>(b->cavs);
     const dim3 block(kT2Width, b->t_rows);
-    switch (b->t_rows) {
-    case 4: hipLaunchKernelGGL((batch_step2_kernel<real, 4>), dim3(grid), block, 0, s, cv, b->tiles2, t0, t1, from); break;
-    case 6: hipLaunchKernelGGL((batch_step2_kernel<real, 6>), dim3(grid), block, 0, s, cv, b->tiles2, t0, t1, from); break;
-    case 10: hipLaunchKernelGGL((batch_step2_kernel<real, 10>), dim3(grid), block, 0, s, cv, b->tiles2, t0, t1, from); break;
-    default: hipLaunchKernelGGL((batch_step2_kernel<real, 16>), dim3(grid), block, 0, s, cv, b->tiles2, t0, t1, from); break;
+    const int K = b->temporal, R = b->t_rows;
+#define DMRT_BKR(KK, RR)                                                                             \
+    if (K == KK && R == RR) {                                                                         \
+        hipLaunchKernelGGL((batch_stepk_kernel<real, RR, KK>), dim3(grid), block, 0, s, cv, b->tiles2, \
+                           t0, t1, from);                                                             \
+        HIPCHK(hipGetLastError());                                                                    \
+        return DMRT_OK;                                                                               \
     }
-    HIPCHK(hipGetLastError());
-    return DMRT_OK;
+    DMRT_BKR(2, 4) DMRT_BKR(2, 6) DMRT_BKR(2, 10) DMRT_BKR(2, 16)
+    DMRT_BKR(3, 6) DMRT_BKR(3, 10) DMRT_BKR(3, 16)
+    DMRT_BKR(4, 10) DMRT_BKR(4, 16)
+#undef DMRT_BKR
+    return DMRT_EINVAL;
 }
 
-// One round: each group in turn advances `steps` steps (pairs of steps in
-// one launch when the two-step kernel is selected).  *flips receives the
+// One round: each group in turn advances `steps` steps (K steps per launch
+// when the K-step kernel is selected).  *flips receives the
 // number of launches per group (each moves the state to the other copy).
 int enqueue_round(dmrt_batch* b, hipStream_t s, int from, int steps, int* flips)
 {
@@ -272,10 +278,10 @@ int enqueue_round(dmrt_batch* b, hipStream_t s, int from, int steps, int* flips)
         nf = 0;
         while (k > 0) {
             int rc;
-            if (b->temporal == 2 && k >= 2) {
-                rc = b->esz == 8 ? launch_range2_t<double>(b, s, b->group_tile2_begin[g], b->group_tile2_begin[g + 1], c)
-                                 : launch_range2_t<float>(b, s, b->group_tile2_begin[g], b->group_tile2_begin[g + 1], c);
-                k -= 2;
+            if (b->temporal >= 2 && k >= b->temporal) {
+                rc = b->esz == 8 ? launch_rangek_t<double>(b, s, b->group_tile2_begin[g], b->group_tile2_begin[g + 1], c)
+                                 : launch_rangek_t<float>(b, s, b->group_tile2_begin[g], b->group_tile2_begin[g + 1], c);
+                k -= b->temporal;
             } else {
                 rc = launch_range(b, s, b->group_tile_begin[g], b->group_tile_begin[g + 1], c);
                 k -= 1;
@@ -450,8 +456,7 @@ int dmrt_batch_set_schedule(dmrt_batch* b, int block_x, int block_y, int order, 
 int dmrt_batch_set_temporal(dmrt_batch* b, int steps_per_launch, int tile_rows)
 {
     if (!b) return DMRT_EINVAL;
-    if (steps_per_launch != 1 && steps_per_launch != 2) return DMRT_EINVAL;
-    if (tile_rows != 4 && tile_rows != 6 && tile_rows != 10 && tile_rows != 16) return DMRT_EINVAL;
+    if (!valid_temporal(steps_per_launch, tile_rows)) return DMRT_EINVAL;
     HIPCHK(hipStreamSynchronize(b->stream));
     drop_graphs(b);
     b->temporal = steps_per_launch;

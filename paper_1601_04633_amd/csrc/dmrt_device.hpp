@@ -521,7 +521,7 @@ static __global__ void __launch_bounds__(256) sum_kernel(const double* __restric
 // Global traffic per node update: (64 R / (62 (R - 2)) + 1) * 14 / 2 words
 // instead of 28.
 constexpr int kT2Width = 64;         // footprint width (one wavefront)
-constexpr int kT2Out = kT2Width - 2;
+constexpr int kT2Out = kT2Width - 2;  // output width of the two-step kernel
 
 template <typename real, int R>
 __device__ __forceinline__ real t2_lds(const real* lds, int q, int ly, int lx)
@@ -546,14 +546,13 @@ __device__ __forceinline__ void t2_phase1(real* lds, const real* __restrict__ fi
     for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
 }
 
-// Phase 2: s(t+2) at output node (x, y) from s(t+1) in LDS, stored to global.
+// Gather of s(t+j-1) for node (x, y) from LDS with the cavity's wall rules.
 template <typename real, int R>
-__device__ __forceinline__ void t2_phase2(const real* lds, real* __restrict__ fo, real* __restrict__ go,
-                                          const real* __restrict__ thw, int n, int pitch, int P, int x,
-                                          int y, int lx, int ly, const Coef<real>& c)
+__device__ __forceinline__ void t2_gather_lds(const real* lds, const real* __restrict__ thw, int n,
+                                              int x, int y, int lx, int ly, const Coef<real>& c,
+                                              real (&f)[9], real (&g)[5])
 {
     const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
-    real f[9], g[5];
     f[0] = t2_lds<real, R>(lds, 0, ly, lx);
     f[1] = hxm ? t2_lds<real, R>(lds, 1, ly, lx - 1) : t2_lds<real, R>(lds, 3, ly, lx);
     f[2] = hym ? t2_lds<real, R>(lds, 2, ly - 1, lx) : t2_lds<real, R>(lds, 4, ly, lx);
@@ -569,7 +568,16 @@ __device__ __forceinline__ void t2_phase2(const real* lds, real* __restrict__ fo
     g[1] = hxm ? t2_lds<real, R>(lds, 10, ly, lx - 1)                                         // Eq. 45
                : c.cabb * thw[y] - t2_lds<real, R>(lds, 12, ly, lx);
     g[3] = hxp ? t2_lds<real, R>(lds, 12, ly, lx + 1) : c.cold - t2_lds<real, R>(lds, 10, ly, lx);
+}
 
+// Last phase: the final step at output node (x, y) from LDS, stored to global.
+template <typename real, int R>
+__device__ __forceinline__ void t2_phase2(const real* lds, real* __restrict__ fo, real* __restrict__ go,
+                                          const real* __restrict__ thw, int n, int pitch, int P, int x,
+                                          int y, int lx, int ly, const Coef<real>& c)
+{
+    real f[9], g[5];
+    t2_gather_lds<real, R>(lds, thw, n, x, y, lx, ly, c, f, g);
     real th, ux, uy;
     collide<real>(f, g, c, th, ux, uy);
     const int k = y * pitch + x;
@@ -579,22 +587,47 @@ __device__ __forceinline__ void t2_phase2(const real* lds, real* __restrict__ fo
     for (int i = 0; i < 5; ++i) go[i * P + k] = g[i];
 }
 
-template <typename real, int R>
-__global__ void __launch_bounds__(kT2Width * R) step2_kernel(StepArgs<real> A)
+// K steps per launch.  Footprint 64 x R nodes, output (64 - 2(K-1)) x
+// (R - 2(K-1)) nodes; phase j computes step t + j on the footprint shrunk by
+// j - 1 nodes on each side (phase 1 from HBM, the others from LDS; the
+// intermediate phases hold their result in registers across a barrier and
+// then overwrite the LDS copy), and the last phase stores to HBM.
+template <typename real, int R, int K>
+__global__ void __launch_bounds__(kT2Width * R) stepk_kernel(StepArgs<real> A)
 {
     __shared__ real lds[14 * R * kT2Width];
+    constexpr int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
+    static_assert(W > 0 && HO > 0, "tile too small for K steps");
     const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
     if (tile >= A.tiles) return;                      // uniform per workgroup
     const int tyt = tile / A.tiles_x;
     const int txt = tile - tyt * A.tiles_x;
     const int lx = threadIdx.x, ly = threadIdx.y;
-    const int x = txt * kT2Out - 1 + lx;
-    const int y = tyt * (R - 2) - 1 + ly;
+    const int x = txt * W - (K - 1) + lx;
+    const int y = tyt * HO - (K - 1) + ly;
     const int n = A.n;
     const bool inside = x >= 0 && x < n && y >= 0 && y < n;
     if (inside) t2_phase1<real, R>(lds, A.fin, A.gin, A.thw, n, A.pitch, A.plane, x, y, lx, ly, A.c);
     __syncthreads();
-    if (!inside || lx < 1 || lx > kT2Out || ly < 1 || ly > R - 2) return;
+#pragma unroll
+    for (int j = 2; j < K; ++j) {
+        const bool act = inside && lx >= j - 1 && lx <= kT2Width - j && ly >= j - 1 && ly <= R - j;
+        real f[9], g[5];
+        if (act) {
+            t2_gather_lds<real, R>(lds, A.thw, n, x, y, lx, ly, A.c, f, g);
+            real th, ux, uy;
+            collide<real>(f, g, A.c, th, ux, uy);
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+        }
+        __syncthreads();
+    }
+    if (!inside || lx < K - 1 || lx > kT2Width - K || ly < K - 1 || ly > R - K) return;
     t2_phase2<real, R>(lds, A.fout, A.gout, A.thw, n, A.pitch, A.plane, x, y, lx, ly, A.c);
 }
 
@@ -771,10 +804,11 @@ __global__ void __launch_bounds__(256) nusselt_kernel(
     }
 }
 
-// Two steps per launch for the batch: tiles are footprints (origin one node
-// left of and below the 62 x (R - 2) output tile) of one member each.
-template <typename real, int R>
-__global__ void __launch_bounds__(kT2Width * R) batch_step2_kernel(
+// K steps per launch for the batch: tiles are footprints (origin K - 1 nodes
+// left of and below the output tile) of one member each; phases as in
+// stepk_kernel, with two barriers per tile around the LDS reuse.
+template <typename real, int R, int K>
+__global__ void __launch_bounds__(kT2Width * R) batch_stepk_kernel(
     const CavityDev<real>* __restrict__ cavs, const TileRef* __restrict__ tiles, int t_begin,
     int t_end, int cur)
 {
@@ -789,7 +823,25 @@ __global__ void __launch_bounds__(kT2Width * R) batch_step2_kernel(
         if (inside)
             t2_phase1<real, R>(lds, cv.f[cur], cv.g[cur], cv.thw, n, cv.pitch, cv.plane, x, y, lx, ly, cv.c);
         __syncthreads();
-        if (inside && lx >= 1 && lx <= kT2Out && ly >= 1 && ly <= R - 2)
+#pragma unroll
+        for (int j = 2; j < K; ++j) {
+            const bool act = inside && lx >= j - 1 && lx <= kT2Width - j && ly >= j - 1 && ly <= R - j;
+            real f[9], g[5];
+            if (act) {
+                t2_gather_lds<real, R>(lds, cv.thw, n, x, y, lx, ly, cv.c, f, g);
+                real th, ux, uy;
+                collide<real>(f, g, cv.c, th, ux, uy);
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
+#pragma unroll
+                for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+            }
+            __syncthreads();
+        }
+        if (inside && lx >= K - 1 && lx <= kT2Width - K && ly >= K - 1 && ly <= R - K)
             t2_phase2<real, R>(lds, cv.f[cur ^ 1], cv.g[cur ^ 1], cv.thw, n, cv.pitch, cv.plane, x, y,
                                lx, ly, cv.c);
         __syncthreads();                              // the next tile reuses the LDS

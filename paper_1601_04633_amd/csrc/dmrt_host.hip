@@ -192,50 +192,28 @@ int launch_nusselt(dmrt_cavity* h, hipStream_t s, int copy, int wall, double* lo
                                     : launch_nusselt_t<float>(h, s, copy, wall, local, avg, to_ring);
 }
 
-template <typename real>
-int launch_step2_t(dmrt_cavity* h, hipStream_t s, int from)
-{
-    StepArgs<real> A;
-    A.fin = fptr<real>(h, from);
-    A.gin = gptr<real>(h, from);
-    A.fout = fptr<real>(h, from ^ 1);
-    A.gout = gptr<real>(h, from ^ 1);
-    A.thw = static_cast<const real*>(h->thw_real);
-    A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
-    const int R = h->t_rows;
-    A.tiles_x = (h->n + kT2Out - 1) / kT2Out;
-    A.tiles = A.tiles_x * ((h->n + R - 3) / (R - 2));
-    A.xcd_remap = h->xcd_remap;
-    A.c = make_coef<real>(h->p, h->d);
-    int nblocks = A.tiles;
-    if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
-    const dim3 grid(nblocks), block(kT2Width, R);
-    switch (R) {
-    case 4: hipLaunchKernelGGL((step2_kernel<real, 4>), grid, block, 0, s, A); break;
-    case 6: hipLaunchKernelGGL((step2_kernel<real, 6>), grid, block, 0, s, A); break;
-    case 10: hipLaunchKernelGGL((step2_kernel<real, 10>), grid, block, 0, s, A); break;
-    default: hipLaunchKernelGGL((step2_kernel<real, 16>), grid, block, 0, s, A); break;
-    }
-    HIPCHK(hipGetLastError());
-    return DMRT_OK;
-}
-
 // Enqueue `count` steps starting at copy `from` with Nu samples where due;
-// `base` is the step counter before the first of them.  Pairs of steps run
-// as one two-step launch when enabled and no sample falls between them.
-// *flips receives the number of launches (each moves the state to the
-// other copy).
+// `base` is the step counter before the first of them.  Groups of K =
+// h->temporal steps run as one launch through LDS when enabled and no
+// sample falls inside the group.  *flips receives the number of launches
+// (each moves the state to the other copy).
 int enqueue_steps(dmrt_cavity* h, hipStream_t s, int from, long base, long count, int* flips)
 {
     int c = from, nflip = 0;
-    const bool two = h->temporal == 2 && h->p.bc_mode == DMRT_BC_CAVITY;
+    const int K = h->p.bc_mode == DMRT_BC_CAVITY ? h->temporal : 1;
     long i = 0;
     while (i < count) {
-        const bool due_mid = h->series_stride > 0 && (base + i + 1) % h->series_stride == 0;
+        bool due_inside = false;
+        if (h->series_stride > 0)
+            for (int j = 1; j < K; ++j) due_inside |= (base + i + j) % h->series_stride == 0;
         int rc;
-        if (two && i + 2 <= count && !due_mid) {
-            rc = h->esz == sizeof(double) ? launch_step2_t<double>(h, s, c) : launch_step2_t<float>(h, s, c);
-            i += 2;
+        if (K >= 2 && i + K <= count && !due_inside) {
+            rc = h->esz == sizeof(double)
+                     ? launch_stepk<double>(h, s, fptr<double>(h, c), gptr<double>(h, c),
+                                            fptr<double>(h, c ^ 1), gptr<double>(h, c ^ 1))
+                     : launch_stepk<float>(h, s, fptr<float>(h, c), gptr<float>(h, c),
+                                           fptr<float>(h, c ^ 1), gptr<float>(h, c ^ 1));
+            i += K;
         } else {
             rc = launch_step(h, s, c);
             i += 1;
@@ -761,9 +739,8 @@ int dmrt_set_launch(dmrt_cavity* h, int block_x, int block_y, int xcd_remap, int
 int dmrt_set_temporal(dmrt_cavity* h, int steps_per_launch, int tile_rows)
 {
     if (!h) return DMRT_EINVAL;
-    if (steps_per_launch != 1 && steps_per_launch != 2) return DMRT_EINVAL;
-    if (tile_rows != 4 && tile_rows != 6 && tile_rows != 10 && tile_rows != 16) return DMRT_EINVAL;
-    if (steps_per_launch == 2 && h->p.bc_mode != DMRT_BC_CAVITY) return DMRT_EINVAL;
+    if (!valid_temporal(steps_per_launch, tile_rows)) return DMRT_EINVAL;
+    if (steps_per_launch >= 2 && h->p.bc_mode != DMRT_BC_CAVITY) return DMRT_EINVAL;
     DeviceGuard g(h->dev);
     HIPCHK(hipStreamSynchronize(h->stream));
     drop_graphs(h);

@@ -91,3 +91,48 @@ struct dmrt_cavity {
         hipError_t e_ = (expr);                                    \
         if (e_ != hipSuccess) return ::dmrt::record_hip(e_, #expr); \
     } while (0)
+
+namespace dmrt {
+
+// Valid (steps per launch, footprint rows) pairs of stepk_kernel.
+inline bool valid_temporal(int k, int rows)
+{
+    if (k == 1) return rows == 4 || rows == 6 || rows == 10 || rows == 16;
+    if (k == 2) return rows == 4 || rows == 6 || rows == 10 || rows == 16;
+    if (k == 3) return rows == 6 || rows == 10 || rows == 16;
+    if (k == 4) return rows == 10 || rows == 16;
+    return false;
+}
+
+// Launches K = h->temporal steps of the cavity from (fin, gin) to (fout, gout)
+// through LDS with footprint rows h->t_rows (K >= 2).
+template <typename real>
+int launch_stepk(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
+                 real* gout)
+{
+    const int K = h->temporal, R = h->t_rows;
+    StepArgs<real> A;
+    A.fin = fin; A.gin = gin; A.fout = fout; A.gout = gout;
+    A.thw = static_cast<const real*>(h->thw_real);
+    A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
+    const int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
+    A.tiles_x = (h->n + W - 1) / W;
+    A.tiles = A.tiles_x * ((h->n + HO - 1) / HO);
+    A.xcd_remap = h->xcd_remap;
+    A.c = make_coef<real>(h->p, h->d);
+    int nblocks = A.tiles;
+    if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
+    const dim3 grid(nblocks), block(kT2Width, R);
+#define DMRT_KR(KK, RR)                                                                \
+    if (K == KK && R == RR) {                                                           \
+        hipLaunchKernelGGL((stepk_kernel<real, RR, KK>), grid, block, 0, s, A);         \
+        return record_hip(hipGetLastError(), "stepk_kernel");                          \
+    }
+    DMRT_KR(2, 4) DMRT_KR(2, 6) DMRT_KR(2, 10) DMRT_KR(2, 16)
+    DMRT_KR(3, 6) DMRT_KR(3, 10) DMRT_KR(3, 16)
+    DMRT_KR(4, 10) DMRT_KR(4, 16)
+#undef DMRT_KR
+    return DMRT_EINVAL;
+}
+
+}  // namespace dmrt

@@ -168,7 +168,7 @@ def test_two_step_forward_does_not_change_gradients():
     tw = inputs.hot_wall_profile(n, 29)
     t0 = inputs.theta_noise(n, 30, amp=1e-2)
     out = []
-    for temporal in ((1, 10), (2, 6), (2, 16)):
+    for temporal in ((1, 10), (2, 6), (2, 16), (3, 10), (4, 16)):
         c = Cavity(n=n, Ra=1e4, Pr=0.01, precision="fp32")
         c.set_temporal(*temporal)
         c.set_hot_wall(tw)

@@ -23,6 +23,10 @@ SCHEDULES = [
     dict(block_x=256, block_y=1, order=0, grid_blocks=0, group_bytes=0, group_steps=10),
     dict(block_x=64, block_y=1, order=2, grid_blocks=300, group_bytes=0, group_steps=7),
     dict(block_x=128, block_y=2, order=1, grid_blocks=0, group_bytes=3 << 20, group_steps=16),
+    dict(block_x=256, block_y=1, order=1, grid_blocks=0, group_bytes=0, group_steps=64, temporal=(3, 16)),
+    dict(block_x=64, block_y=4, order=2, grid_blocks=500, group_bytes=3 << 20, group_steps=10,
+         temporal=(3, 10)),
+    dict(block_x=256, block_y=1, order=0, grid_blocks=0, group_bytes=0, group_steps=11, temporal=(4, 16)),
 ]
 
 

@@ -131,8 +131,8 @@ def test_full_size_1024_matches_oracle(oracle_mod, precision, tol):
     after a few steps (the oracle advances 1M nodes per step slowly)."""
     print(f"[parity] 1024^2 {precision}", flush=True)
     o, c = _pair(oracle_mod, 1024, 1e5, 0.001, precision=precision)
-    c.set_launch(256, 1, 1, 64)
-    c.set_temporal(2, 6)
+    c.set_launch(256, 1, 1, 60)
+    c.set_temporal(3, 16)
     o.step(6)
     c.step(6)
     _compare_fields(o, c, tol, names=("theta",) if precision == "fp32" else ("U", "V", "theta", "P"))
@@ -279,11 +279,12 @@ def test_case1_physics_against_paper():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("rows", [4, 6, 10, 16])
-def test_two_step_launch_equals_single_steps(precision, rows):
-    """Two steps per launch through LDS give bitwise the state of single
+@pytest.mark.parametrize("k,rows", [(2, 4), (2, 6), (2, 10), (2, 16), (3, 6), (3, 10), (3, 16),
+                                    (4, 10), (4, 16)])
+def test_multi_step_launch_equals_single_steps(precision, k, rows):
+    """K steps per launch through LDS give bitwise the state of single
     steps, for ragged sizes, odd step counts, graph replay and Nu sampling
-    that splits pairs."""
+    that splits groups."""
     from paper_1601_04633_amd.dmrt import Cavity
     for n in (4, 5, 37, 62, 63, 100, 130, 257):
         th0 = inputs.theta_noise(n, 40 + n, amp=1e-2)
@@ -292,20 +293,21 @@ def test_two_step_launch_equals_single_steps(precision, rows):
         ref.nu_series(7, 100)
         ref.step(131)
         two = Cavity(n=n, Ra=2e4, Pr=0.01, precision=precision)
-        two.set_temporal(2, rows)
+        two.set_temporal(k, rows)
         two.set_theta(th0)
         two.nu_series(7, 100)
         two.step(67)
         two.step(64)
         fa, ga = ref.raw_state()
         fb, gb = two.raw_state()
-        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), (n, rows)
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), (n, k, rows)
         np.testing.assert_array_equal(ref.nu_series_read(), two.nu_series_read())
 
 
-def test_two_step_fp64_matches_oracle(oracle_mod):
+@pytest.mark.parametrize("k,rows", [(2, 10), (3, 10), (4, 16)])
+def test_multi_step_fp64_matches_oracle(oracle_mod, k, rows):
     o, c = _pair(oracle_mod, 100, 1e4, 0.01)
-    c.set_temporal(2, 10)
+    c.set_temporal(k, rows)
     o.step(151)
     c.step(151)
     _compare_fields(o, c, 1e-12)
