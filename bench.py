@@ -31,11 +31,9 @@ METRIC = "MLUPS (D2Q9+D2Q5 node updates/s), % HBM roofline; adjoint/forward cost
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD published)
 WORDS_PER_NODE = 28            # 14 populations read + 14 written per node update
 TRAFFIC_FILES = {
-    "step_kernel<float, BC_CAVITY>": os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json"),
-    "stepk_kernel<float, 6, 2>": os.path.join(ROOT, "profiles", "step2_kernel_cavity_1024_fp32_traffic.json"),
-    "stepk_kernel<float, 10, 3>": os.path.join(ROOT, "profiles", "step3_kernel_cavity_1024_fp32_traffic.json"),
-    "stepk_kernel<float, 16, 3>": os.path.join(ROOT, "profiles", "step3r16_kernel_cavity_1024_fp32_traffic.json"),
-    "stepk_kernel<float, 16, 4>": os.path.join(ROOT, "profiles", "step4_kernel_cavity_1024_fp32_traffic.json"),
+    "step_kernel<float, 0>": os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json"),
+    "stepk_kernel<float, 16, 3>": os.path.join(ROOT, "profiles",
+                                               "stepk_kernel_K3_R16_cavity_1024_fp32_traffic.json"),
 }
 # launch configuration timed by default (the fastest for this workload on
 # MI355X): three steps per launch through LDS, 64 x 16 footprints,
@@ -66,7 +64,7 @@ def measured_traffic(bytes_alg_per_launch, kernel):
             t = json.load(fh)
     except (OSError, ValueError, KeyError):
         return None
-    if t.get("kernel_hash") != kernel_hash():
+    if t.get("kernel_hash") != kernel_hash() or t.get("kernel") != kernel:
         return None
     return t.get("bytes_per_launch")
 
@@ -282,13 +280,13 @@ def main():
     spl = temporal[0]                       # node updates per node per launch
     ms_launch = ms_step * spl
     # algorithmic bytes of one launch: every population read and written once
-    # per launch, i.e. 28 words per node per launch (14 words per node update
-    # for the two-step kernel, 28 for the single-step kernel)
+    # per launch, i.e. 28 words per node per launch, 28 / K words per node
+    # update when a launch advances K steps
     alg_bytes = WORDS_PER_NODE * esz * n * n
     achieved = alg_bytes / (ms_launch * 1e-3) / 1e9
     single_equiv = WORDS_PER_NODE * esz * n * n * spl / (ms_launch * 1e-3) / 1e9
     kname = (f"stepk_kernel<{'float' if esz == 4 else 'double'}, {temporal[1]}, {spl}>" if spl >= 2
-             else f"step_kernel<{'float' if esz == 4 else 'double'}, BC_CAVITY>")
+             else f"step_kernel<{'float' if esz == 4 else 'double'}, 0>")
     traffic = measured_traffic(alg_bytes, kname) if n == 1024 and prec == "fp32" else None
     log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic per launch "
         f"({single_equiv:.1f} GB/s single-step equivalent), {ms_launch*1e3:.2f} us/launch, Nu {nu:.5f}")
