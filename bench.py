@@ -169,7 +169,8 @@ def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp3
     """Gradient of the mean hot-wall Nu over the last K of N steps (256^2,
     FP32, checkpoints every C): time per step of the plain forward, of the
     checkpointed forward that also accumulates J, and of the backward
-    (segment recompute + adjoint kernel)."""
+    (segment recompute + adjoint kernel), each in its fastest launch
+    configuration."""
     import torch
     from paper_1601_04633_amd import autotune, inputs
     from paper_1601_04633_amd.dmrt import Cavity
@@ -193,6 +194,9 @@ def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp3
     # the forward reference is the fastest plain stepping of this cavity
     best, _, _ = autotune.tune_cavity(c, stream_ptr=stream.cuda_stream, use_cache=False)
     c.set_theta(t0)
+    bwd, _, bwd_trials = autotune.tune_adjoint(c, ckpt_every=C, stream_ptr=stream.cuda_stream,
+                                               use_cache=False)
+    c.set_theta(t0)
     c.step(1000)                                  # warm-up, graphs
     c.sync()
     _, t_plain = timed(lambda: c.step(N))
@@ -207,6 +211,9 @@ def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp3
                                "steps_per_launch_rows": list(best["temporal"])},
             "forward_us_per_step": round(t_plain / N * 1e6, 3),
             "checkpointed_forward_us_per_step": round(t_fwd / N * 1e6, 3),
+            "backward_launch": {"steps_per_launch_rows": list(bwd),
+                                "tuning_us_per_step": {f"K{k}R{r}": round(t * 1e6, 3)
+                                                       for (k, r), t in bwd_trials}},
             "backward_us_per_step": round(t_bwd / N * 1e6, 3),
             "backward_over_forward": round(t_bwd / t_plain, 3),
             "forward_plus_backward_over_forward": round((t_fwd + t_bwd) / t_plain, 3),

@@ -234,7 +234,9 @@ int dmrt_destroy(dmrt_cavity *h);
  * profile theta_w(y) (Eq. 45 and Eq. 18) and theta0.  Only DMRT_BC_CAVITY.
  * The forward stores a checkpoint every ckpt_every steps; the backward
  * recomputes each segment from its checkpoint and runs the hand-written
- * adjoint step kernel.  Device memory: (ceil(nsteps/ckpt_every) +
+ * adjoint step kernel (the discrete adjoint of the step: the transposed
+ * collision Jacobian at each node, then the transposed streaming and wall
+ * map).  Device memory: (ceil(nsteps/ckpt_every) +
  * ckpt_every + 2) states of 14 n^2 elements, held until
  * dmrt_adjoint_release or dmrt_destroy.
  * ------------------------------------------------------------------------ */
@@ -253,6 +255,13 @@ int dmrt_adjoint_backward(dmrt_cavity *h, double *dJ_dthetaw, double *dJ_dtheta0
 /* dmrt_adjoint_forward followed by dmrt_adjoint_backward. */
 int dmrt_adjoint_nu(dmrt_cavity *h, long nsteps, long avg_last, long ckpt_every, double *J,
                     double *dJ_dthetaw, double *dJ_dtheta0);
+
+/* Adjoint steps (and recompute steps) per backward launch: 1, or 2..4
+ * through LDS with footprints of 64 x tile_rows threads (the same pairs as
+ * dmrt_set_temporal).  The gradients do not depend on it (bitwise).
+ * Releases the adjoint buffers.  EINVAL for an unsupported pair or a
+ * non-cavity handle.  Synchronises. */
+int dmrt_adjoint_set_temporal(dmrt_cavity *h, int steps_per_launch, int tile_rows);
 
 /* Free the checkpoint, segment and adjoint buffers. */
 int dmrt_adjoint_release(dmrt_cavity *h);

@@ -11,6 +11,7 @@ order, workgroups per launch, and cavity groups sized for the 256 MB
 last-level cache that run several steps before the next group.
 Single-cavity dimensions: steps per launch and tile rows
 (dmrt_set_temporal), tile shape and die-aware tile order (dmrt_set_launch).
+Adjoint: steps per backward launch and tile rows (dmrt_adjoint_set_temporal).
 """
 from __future__ import annotations
 
@@ -205,6 +206,39 @@ def tune_cavity(cavity, stream_ptr=None, steps=256, use_cache=True, verbose=Fals
     apply_cavity(cavity, best)
     _store_cache(key, {"temporal": list(best["temporal"]), "block": list(best["block"]),
                        "xcd_remap": best["xcd_remap"], "sec_per_step": best_t})
+    return best, best_t, trials
+
+
+ADJOINT_SPACE = [(3, 10), (2, 6), (2, 10), (2, 16), (3, 16), (4, 16), (4, 10), (1, 10)]
+
+
+def tune_adjoint(cavity, nsteps=2000, avg_last=400, ckpt_every=500, stream_ptr=None, use_cache=True,
+                 verbose=False):
+    """Pick the fastest steps-per-launch and footprint rows for the backward
+    pass of dmrt_adjoint_nu (gradients do not depend on it); leaves it
+    applied.  The cavity's theta0 must be set."""
+    key = f"adjoint|{_arch()}|{'fp64' if cavity.params.precision == 1 else 'fp32'}|{cavity.n}|{ckpt_every}"
+    if use_cache:
+        hit = _load_cache().get(key)
+        if hit:
+            cavity.adjoint_set_temporal(*hit["temporal"])
+            return tuple(hit["temporal"]), hit.get("sec_per_step"), []
+    start, stop = _timer(stream_ptr)
+    trials = []
+    for kr in ADJOINT_SPACE:
+        cavity.adjoint_set_temporal(*kr)
+        cavity.adjoint_forward(nsteps, avg_last, ckpt_every)
+        cavity.adjoint_backward()                 # buffers and captured graphs
+        cavity.adjoint_forward(nsteps, avg_last, ckpt_every)
+        start()
+        cavity.adjoint_backward()
+        t = stop() / nsteps
+        trials.append((kr, t))
+        if verbose:
+            print(f"[autotune] adjoint n={cavity.n} backward {kr} {t * 1e6:.2f} us/step", flush=True)
+    best, best_t = min(trials, key=lambda e: e[1])
+    cavity.adjoint_set_temporal(*best)
+    _store_cache(key, {"temporal": list(best), "sec_per_step": best_t})
     return best, best_t, trials
 
 

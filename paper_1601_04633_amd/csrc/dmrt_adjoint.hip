@@ -9,12 +9,14 @@
 // FP64.  J = H / (3 dT n K) * sum over rows and window steps.
 // Backward: segments of C steps, newest first.  Each segment's states are
 // recomputed from its checkpoint into one of two segment buffers; the
-// adjoint step kernel then runs from the segment's last step to its first
-// (lambda ping-pong), and each of its launches also carries one recompute
-// step of the next-older segment into the other buffer (independent work,
-// so the small per-step launches fill the chip).  A captured graph of one
-// full segment is replayed for every full segment; the segment's first step
-// index is read from device memory, updated before each replay.
+// adjoint step kernel then runs from the segment's last step to its first,
+// carrying mu = the adjoint of the pre-collision state in a ping-pong pair
+// (one or K steps per launch), and each of its launches also carries as
+// many recompute steps of the next-older segment into the other buffer
+// (independent work, so the small launches fill the chip).  A captured
+// graph of one full segment is replayed for every full segment; the
+// segment's first step index is read from device memory, updated before
+// each replay.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +40,7 @@ struct AdjointState {
     size_t slot_elems = 0;       // 14 planes
     void* ckpt = nullptr;        // nseg slots: s(k C)
     void* seg[2] = {nullptr, nullptr};   // two buffers of C slots: s(k C + j)
-    void* lam = nullptr;         // 2 slots
+    void* lam = nullptr;         // 2 slots of mu
     double* nu_acc = nullptr;    // n
     double* gthw = nullptr;      // n
     double* grad0 = nullptr;     // n^2
@@ -54,6 +56,7 @@ struct AdjointState {
     int fwd_flips[2][2] = {{0, 0}, {0, 0}};
     hipGraphExec_t fwd[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipGraph_t fwd_def[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int bwd_flips[2][2] = {{0, 0}, {0, 0}};
     hipGraphExec_t bwd[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipGraph_t bwd_def[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
@@ -191,63 +194,128 @@ AdjArgs<real> adj_args(const dmrt_cavity* h, const AdjointState* a)
     A.seed0 = real(-9.0 * c);
     A.seed1 = real(c);
     A.cabb = (4.0 + h->d.a) / 10.0;
+    A.slot = (long)a->slot_elems;
     A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
     A.tiles_x = (h->n + h->block_x - 1) / h->block_x;
     A.tiles = A.tiles_x * ((h->n + h->block_y - 1) / h->block_y);
+    A.xcd_remap = 0;
     A.c = make_coef<real>(h->p, h->d);
     return A;
 }
 
-// Forward recompute of slots [r0, r1) of segment buffer `b` (slot r from r - 1).
-template <typename real>
-int enqueue_recompute(dmrt_cavity* h, AdjointState* a, hipStream_t s, int b, long r0, long r1)
+// Tile grid of the K-step kernels (output tiles of (64 - 2(K-1)) x (R - 2(K-1))).
+inline void k_geometry(int n, int K, int R, int& tiles_x, int& tiles)
 {
-    const size_t se = a->slot_elems, P = h->plane;
-    for (long r = r0; r < r1; ++r) {
-        real* src = slot<real>(a->seg[b], se, r - 1);
-        real* dst = slot<real>(a->seg[b], se, r);
-        int rc = launch_fwd<real>(h, a, s, src, src + 9 * P, dst, dst + 9 * P, false);
-        if (rc) return rc;
+    const int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
+    tiles_x = (n + W - 1) / W;
+    tiles = tiles_x * ((n + HO - 1) / HO);
+}
+
+// The K-step backward kernels for (K, R) = (h->adj_temporal, h->adj_rows):
+// adjoint only (A), recompute only (F), or both in one launch.
+template <typename real>
+int launch_adjk(const dmrt_cavity* h, hipStream_t s, const AdjArgs<real>* A, const StepArgs<real>* F)
+{
+    const int K = h->adj_temporal, R = h->adj_rows;
+    const dim3 block(kT2Width, R);
+    const long slot = A ? A->slot : (long)h->adj->slot_elems;
+    auto padded = [](int t) { return (t + 7) / 8 * 8; };
+#define DMRT_AKR(KK, RR)                                                                               \
+    if (K == KK && R == RR) {                                                                           \
+        if (A && F)                                                                                     \
+            hipLaunchKernelGGL((adjk_fused_kernel<real, RR, KK>), dim3(A->tiles + F->tiles), block, 0, s, \
+                               *A, *F);                                                                 \
+        else if (A)                                                                                     \
+            hipLaunchKernelGGL((adjk_kernel<real, RR, KK>),                                             \
+                               dim3(A->xcd_remap ? padded(A->tiles) : A->tiles), block, 0, s, *A);      \
+        else                                                                                            \
+            hipLaunchKernelGGL((stepk_all_kernel<real, RR, KK>),                                        \
+                               dim3(F->xcd_remap ? padded(F->tiles) : F->tiles), block, 0, s, *F, slot); \
+        return record_hip(hipGetLastError(), "adjoint K-step kernel");                                 \
     }
-    return DMRT_OK;
+    DMRT_AKR(2, 4) DMRT_AKR(2, 6) DMRT_AKR(2, 10) DMRT_AKR(2, 16)
+    DMRT_AKR(3, 6) DMRT_AKR(3, 10) DMRT_AKR(3, 16)
+    DMRT_AKR(4, 10) DMRT_AKR(4, 16)
+#undef DMRT_AKR
+    return DMRT_EINVAL;
 }
 
 // Backward of one segment held in buffer `b` (len states), pipelined with
 // the recompute of the next-older segment into buffer b ^ 1 (rec_len
-// states, slot 0 already filled; 0 when there is none): launch t runs the
-// adjoint of the segment's step len - t and the forward recompute of slot
-// t + 1 of the other buffer.
+// states, slot 0 already filled; 0 when there is none).  Adjoint launches
+// run from the segment's newest step down, K = h->adj_temporal steps each
+// while at least K remain, then single steps; recompute launches fill slots
+// 1, 2, ... of the other buffer the same way.  The i-th adjoint launch and
+// the i-th recompute launch share one kernel when they take the same number
+// of steps.  *flips receives the number of adjoint launches (mu copy
+// changes).
 template <typename real>
 int enqueue_segment(dmrt_cavity* h, AdjointState* a, hipStream_t s, int b, long len, long rec_len,
-                    int lam_from)
+                    int lam_from, int* flips)
 {
     const size_t se = a->slot_elems, P = h->plane;
-    AdjArgs<real> A = adj_args<real>(h, a);
-    int l = lam_from;
-    for (long t = 0; t < len; ++t) {
-        const long j = len - t;
-        real* st = slot<real>(a->seg[b], se, j - 1);
-        A.fs = st;
-        A.gs = st + 9 * P;
-        A.lin = slot<real>(a->lam, se, l);
-        A.lout = slot<real>(a->lam, se, l ^ 1);
-        A.j = (int)j;
-        const long r = t + 1;
-        if (r < rec_len) {
+    const int K = h->adj_temporal, R = h->adj_rows;
+    const AdjArgs<real> A1 = adj_args<real>(h, a);
+    AdjArgs<real> AK = A1;
+    if (K >= 2) {
+        k_geometry(h->n, K, R, AK.tiles_x, AK.tiles);
+        AK.xcd_remap = h->xcd_remap;
+    }
+    int l = lam_from, nl = 0;
+    long j = len;      // the next adjoint launch forms mu(n0 + j) from slot j - 1
+    long r = 1;        // the next recompute slot
+    while (j >= 1 || r < rec_len) {
+        const int ka = j < 1 ? 0 : (K >= 2 && j >= K ? K : 1);
+        const int kr = r >= rec_len ? 0 : (K >= 2 && r + K - 1 <= rec_len - 1 ? K : 1);
+        AdjArgs<real> A = ka >= 2 ? AK : A1;
+        if (ka) {
+            real* st = slot<real>(a->seg[b], se, j - 1);
+            A.fs = st;
+            A.gs = st + 9 * P;
+            A.lin = slot<real>(a->lam, se, l);
+            A.lout = slot<real>(a->lam, se, l ^ 1);
+            A.j = (int)j;
+        }
+        StepArgs<real> F{};
+        if (kr) {
             real* src = slot<real>(a->seg[b ^ 1], se, r - 1);
             real* dst = slot<real>(a->seg[b ^ 1], se, r);
-            const StepArgs<real> R = step_args<real>(h, src, src + 9 * P, dst, dst + 9 * P);
-            hipLaunchKernelGGL((adj_fused_kernel<real>), dim3(A.tiles + R.tiles),
-                               dim3(h->block_x, h->block_y), 0, s, A, R);
-        } else {
-            hipLaunchKernelGGL((adj_step_kernel<real>), dim3(A.tiles), dim3(h->block_x, h->block_y), 0,
-                               s, A);
+            F = step_args<real>(h, src, src + 9 * P, dst, dst + 9 * P);
+            if (kr >= 2) k_geometry(h->n, K, R, F.tiles_x, F.tiles);
         }
-        HIPCHK(hipGetLastError());
-        l ^= 1;
+        int rc = DMRT_OK;
+        if (ka >= 2 && kr >= 2) {
+            A.xcd_remap = 0;
+            F.xcd_remap = 0;
+            rc = launch_adjk<real>(h, s, &A, &F);
+        } else if (ka == 1 && kr == 1) {
+            hipLaunchKernelGGL((adj_fused_kernel<real>), dim3(A.tiles + F.tiles), dim3(h->block_x, h->block_y),
+                               0, s, A, F);
+            rc = record_hip(hipGetLastError(), "adj_fused_kernel");
+        } else {
+            if (ka >= 2) {
+                rc = launch_adjk<real>(h, s, &A, nullptr);
+            } else if (ka == 1) {
+                hipLaunchKernelGGL((adj_step_kernel<real>), dim3(A.tiles), dim3(h->block_x, h->block_y), 0,
+                                   s, A);
+                rc = record_hip(hipGetLastError(), "adj_step_kernel");
+            }
+            if (!rc && kr >= 2) rc = launch_adjk<real>(h, s, nullptr, &F);
+            else if (!rc && kr == 1) rc = launch_fwd<real>(h, a, s, F.fin, F.gin, F.fout, F.gout, false);
+        }
+        if (rc) return rc;
+        if (ka) { j -= ka; l ^= 1; ++nl; }
+        r += kr;
     }
-    if (rec_len - 1 > len) return enqueue_recompute<real>(h, a, s, b ^ 1, len + 1, rec_len);
+    if (flips) *flips = nl;
     return DMRT_OK;
+}
+
+// Recompute of slots [1, len) of buffer b on its own (the newest segment).
+template <typename real>
+int enqueue_recompute(dmrt_cavity* h, AdjointState* a, hipStream_t s, int b, long len)
+{
+    return enqueue_segment<real>(h, a, s, b ^ 1, 0, len, 0, nullptr);
 }
 
 int ensure_state(dmrt_cavity* h, long N, long K, long C)
@@ -329,9 +397,9 @@ int backward_t(dmrt_cavity* h, double* gw, double* g0)
     const size_t se = a->slot_elems, esz = h->esz;
     const double c = h->d.H / (3.0 * (h->p.theta_hot - h->p.theta_cold) * h->n * a->K);
     const dim3 ib(64, 4), ig((h->n + 63) / 64, (h->n + 3) / 4);
-    // lambda(N) = dJ/ds(N); step N is always in the window
-    hipLaunchKernelGGL((adj_seed_kernel<real>), ig, ib, 0, h->stream, slot<real>(a->lam, se, 0), h->n,
-                       h->pitch, h->plane, real(-9.0 * c), real(c));
+    // mu(N+1) = 0, so the first adjoint step forms lambda(N) = dJ/ds(N)
+    hipLaunchKernelGGL((adj_zero_kernel<real>), ig, ib, 0, h->stream, slot<real>(a->lam, se, 0), h->n,
+                       h->pitch, h->plane);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemsetAsync(a->gthw, 0, h->n * sizeof(double), h->stream));
     auto seg_len = [&](int k) { return std::min<long>(a->C, a->N - (long)k * a->C); };
@@ -344,7 +412,7 @@ int backward_t(dmrt_cavity* h, double* gw, double* g0)
     const int last = a->nseg - 1;
     int rc;
     if ((rc = load_ckpt(last, last & 1))) return rc;
-    if ((rc = enqueue_recompute<real>(h, a, h->stream, last & 1, 1, seg_len(last)))) return rc;
+    if ((rc = enqueue_recompute<real>(h, a, h->stream, last & 1, seg_len(last)))) return rc;
     int l = 0;
     for (int k = last; k >= 0; --k) {
         const int b = k & 1;
@@ -357,7 +425,7 @@ int backward_t(dmrt_cavity* h, double* gw, double* g0)
             // sequence: replay one captured graph per (lambda parity, buffer)
             if (!a->bwd[l][b]) {
                 HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-                rc = enqueue_segment<real>(h, a, h->cap_stream, b, len, rec_len, l);
+                rc = enqueue_segment<real>(h, a, h->cap_stream, b, len, rec_len, l, &a->bwd_flips[l][b]);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
                 if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -367,14 +435,16 @@ int backward_t(dmrt_cavity* h, double* gw, double* g0)
                 a->bwd_def[l][b] = g;
             }
             HIPCHK(hipGraphLaunch(a->bwd[l][b], h->stream));
+            if (a->bwd_flips[l][b] & 1) l ^= 1;
         } else {
-            if ((rc = enqueue_segment<real>(h, a, h->stream, b, len, rec_len, l))) return rc;
+            int nl = 0;
+            if ((rc = enqueue_segment<real>(h, a, h->stream, b, len, rec_len, l, &nl))) return rc;
+            if (nl & 1) l ^= 1;
         }
-        if (len & 1) l ^= 1;
     }
     hipLaunchKernelGGL((adj_init_grad_kernel<real>), ig, ib, 0, h->stream, slot<real>(a->lam, se, l),
                        h->theta0, h->n, h->pitch, h->plane, make_coef<real>(h->p, h->d), real(h->d.w0),
-                       real(h->d.wm), a->grad0);
+                       real(h->d.wm), a->win_start <= 0, real(-9.0 * c), real(c), a->grad0);
     HIPCHK(hipGetLastError());
     const size_t nn = (size_t)h->n * h->n;
     std::vector<double> tw(h->n);
@@ -417,6 +487,20 @@ int dmrt_adjoint_nu(dmrt_cavity* h, long nsteps, long avg_last, long ckpt_every,
     int rc = dmrt_adjoint_forward(h, nsteps, avg_last, ckpt_every, J);
     if (rc) return rc;
     return dmrt_adjoint_backward(h, dJ_dthetaw, dJ_dtheta0);
+}
+
+int dmrt_adjoint_set_temporal(dmrt_cavity* h, int steps_per_launch, int tile_rows)
+{
+    if (!h || !valid_temporal(steps_per_launch, tile_rows)) return DMRT_EINVAL;
+    if (h->p.bc_mode != DMRT_BC_CAVITY) return DMRT_EINVAL;
+    (void)hipStreamSynchronize(h->stream);
+    h->adj_temporal = steps_per_launch;
+    h->adj_rows = tile_rows;
+    if (h->adj) {
+        free_adjoint(h->adj);
+        h->adj = nullptr;
+    }
+    return DMRT_OK;
 }
 
 int dmrt_adjoint_release(dmrt_cavity* h)

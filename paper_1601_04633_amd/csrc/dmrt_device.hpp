@@ -273,6 +273,10 @@ template <typename real>
 __device__ __forceinline__ void collide_vjp(const real (&f)[9], const real (&g)[5], const Coef<real>& c,
                                             real (&lf)[9], real (&lg)[5])
 {
+    // No multiply-add contraction here: the compiler's choice would differ
+    // between the kernels this is inlined into, and the adjoint must give
+    // the same bits whatever the number of steps per launch.
+#pragma clang fp contract(off)
     const real two = real(2), three = real(3), six = real(6);
     const real u = (f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6]);
     const real v = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
@@ -345,27 +349,76 @@ __device__ __forceinline__ void collide_vjp(const real (&f)[9], const real (&g)[
 
 template <typename real>
 struct AdjArgs {
-    const real* __restrict__ fs;     // s(n-1): f planes
-    const real* __restrict__ gs;     // s(n-1): g planes
-    const real* __restrict__ lin;    // lambda(n): 14 planes (f then g)
-    real* __restrict__ lout;         // lambda(n-1)
+    const real* __restrict__ fs;     // s(m-1): f planes (segment slot j - 1)
+    const real* __restrict__ gs;     // s(m-1): g planes
+    const real* __restrict__ lin;    // mu(m+1): 14 planes (f then g)
+    real* __restrict__ lout;         // mu(m), or mu(m-K+1) for K steps per launch
     const real* __restrict__ thw;
     double* __restrict__ gthw;       // accumulates dJ/dtheta_w (anti-bounce-back links)
     const int* __restrict__ n0p;     // step index of the segment's first state
-    int j;                           // this launch is the adjoint of step *n0p + j
+    int j;                           // m = *n0p + j is the newest step of this launch
     int win_start;                   // first step of the objective window
     real seed0, seed1;               // dJ/dg*_i(m) at x = 0 and x = 1 for m in the window
     double cabb;                     // Eq. 45 constant in FP64
+    long slot;                       // elements between consecutive segment slots
     int n, pitch, plane, tiles_x, tiles;
+    int xcd_remap;
     Coef<real> c;
 };
 
-// Adjoint of step n for the cavity: lambda(n-1) = S^T C'(p(n))^T lambda(n)
-// + dJ/ds(n-1), with p(n) the pre-collision state gathered from s(n-1)
-// exactly as in the forward step, S the streaming/wall map.  S is a
-// permutation (with sign -1 on the anti-bounce-back links), so the
-// transposed streaming is a push: every lambda(n-1) entry has exactly one
-// writer.  The anti-bounce-back constant's derivative feeds dJ/dtheta_w.
+// dJ/dg*_i(m) at column x: the Nusselt objective (Eqs. 18-19) reads the
+// temperatures of the two columns next to the hot wall on window steps.
+template <typename real>
+__device__ __forceinline__ real adj_seed_at(int x, bool win, real s0, real s1)
+{
+    return win ? (x == 0 ? s0 : (x == 1 ? s1 : real(0))) : real(0);
+}
+
+// lambda(m) = S^T mu(m+1) + dJ/ds(m) at node (x, y), with mu(m+1) in global
+// memory.  The streaming/wall map S of step m + 1 sends population i of
+// s(m) at r to r + e_i, or, across a wall, back into population opp(i) at
+// r (sign -1 on the anti-bounce-back links of Eq. 45), so its transpose is
+// a pull in the direction opposite to the forward gather.
+template <typename real>
+__device__ __forceinline__ void adj_pull(const real* __restrict__ mu, int n, int pitch, int P, int x,
+                                         int y, real sd, real (&lf)[9], real (&lg)[5])
+{
+    const int k = y * pitch + x;
+    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
+    lf[0] = mu[k];
+    lf[1] = hxp ? mu[1 * P + k + 1] : mu[3 * P + k];
+    lf[2] = hyp ? mu[2 * P + k + pitch] : mu[4 * P + k];
+    lf[3] = hxm ? mu[3 * P + k - 1] : mu[1 * P + k];
+    lf[4] = hym ? mu[4 * P + k - pitch] : mu[2 * P + k];
+    lf[5] = (hxp && hyp) ? mu[5 * P + k + pitch + 1] : mu[7 * P + k];
+    lf[6] = (hxm && hyp) ? mu[6 * P + k + pitch - 1] : mu[8 * P + k];
+    lf[7] = (hxm && hym) ? mu[7 * P + k - pitch - 1] : mu[5 * P + k];
+    lf[8] = (hxp && hym) ? mu[8 * P + k - pitch + 1] : mu[6 * P + k];
+    const real* __restrict__ mg = mu + 9 * P;
+    lg[0] = mg[k] + sd;
+    lg[1] = hxp ? mg[1 * P + k + 1] + sd : sd - mg[3 * P + k];         // Eq. 45, right wall
+    lg[2] = hyp ? mg[2 * P + k + pitch] + sd : mg[4 * P + k] + sd;      // Eq. 44
+    lg[3] = hxm ? mg[3 * P + k - 1] + sd : sd - mg[1 * P + k];         // Eq. 45, left wall
+    lg[4] = hym ? mg[4 * P + k - pitch] + sd : mg[2 * P + k] + sd;
+}
+
+// One adjoint node update: mu(m) = C'(p(m))^T lambda(m), with p(m) gathered
+// from s(m-1) exactly as in the forward step.  The derivative of the
+// anti-bounce-back constant feeds dJ/dtheta_w at the hot wall.
+template <typename real>
+__device__ __forceinline__ void adj_node(const real* __restrict__ fs, const real* __restrict__ gs,
+                                         const AdjArgs<real>& A, int x, int y, real (&lf)[9],
+                                         real (&lg)[5])
+{
+    real f[9], g[5];
+    gather<real, BC_CAVITY>(fs, gs, A.thw, A.n, A.pitch, A.plane, x, y, A.c, f, g);
+    collide_vjp<real>(f, g, A.c, lf, lg);
+}
+
+// Adjoint of step m for the cavity: lambda(m) = S^T mu(m+1) + dJ/ds(m),
+// mu(m) = C'(p(m))^T lambda(m); the segment's slot j - 1 holds s(m-1).
+// Storing mu rather than lambda makes the transposed streaming a pull, so
+// every thread writes only its own node.
 template <typename real>
 __device__ __forceinline__ void adj_tile(const AdjArgs<real>& A, int tile)
 {
@@ -375,50 +428,17 @@ __device__ __forceinline__ void adj_tile(const AdjArgs<real>& A, int tile)
     const int y = ty * blockDim.y + threadIdx.y;
     const int n = A.n;
     if (x >= n || y >= n) return;
-    const int pitch = A.pitch, P = A.plane;
-    const int k = y * pitch + x;
-
-    real f[9], g[5];
-    gather<real, BC_CAVITY>(A.fs, A.gs, A.thw, n, pitch, P, x, y, A.c, f, g);
+    const int P = A.plane, k = y * A.pitch + x;
+    const int m = *A.n0p + A.j;
     real lf[9], lg[5];
+    adj_pull<real>(A.lin, n, A.pitch, P, x, y, adj_seed_at<real>(x, m >= A.win_start, A.seed0, A.seed1),
+                   lf, lg);
+    adj_node<real>(A.fs, A.gs, A, x, y, lf, lg);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lf[i] = A.lin[i * P + k];
+    for (int i = 0; i < 9; ++i) A.lout[i * P + k] = lf[i];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lg[i] = A.lin[(9 + i) * P + k];
-    collide_vjp<real>(f, g, A.c, lf, lg);
-
-    const int m = *A.n0p + A.j - 1;                 // lambda(m) is being formed
-    const bool win = m >= A.win_start;
-    const real s0 = win ? A.seed0 : real(0), s1 = win ? A.seed1 : real(0);
-
-    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
-    real* __restrict__ lo = A.lout;
-    // D2Q9: the population that arrived from r - e_i, or bounced at r
-    lo[k] = lf[0];
-    if (hxm) lo[1 * P + k - 1] = lf[1]; else lo[3 * P + k] = lf[1];
-    if (hym) lo[2 * P + k - pitch] = lf[2]; else lo[4 * P + k] = lf[2];
-    if (hxp) lo[3 * P + k + 1] = lf[3]; else lo[1 * P + k] = lf[3];
-    if (hyp) lo[4 * P + k + pitch] = lf[4]; else lo[2 * P + k] = lf[4];
-    if (hxm && hym) lo[5 * P + k - pitch - 1] = lf[5]; else lo[7 * P + k] = lf[5];
-    if (hxp && hym) lo[6 * P + k - pitch + 1] = lf[6]; else lo[8 * P + k] = lf[6];
-    if (hxp && hyp) lo[7 * P + k + pitch + 1] = lf[7]; else lo[5 * P + k] = lf[7];
-    if (hxm && hyp) lo[8 * P + k + pitch - 1] = lf[8]; else lo[6 * P + k] = lf[8];
-    // D2Q5, plus the temperature seed of the Nusselt objective on the two
-    // columns next to the hot wall
-    real* __restrict__ lg_o = lo + 9 * P;
-    const real sx = x == 0 ? s0 : (x == 1 ? s1 : real(0));
-    const real sxm = x == 1 ? s0 : (x == 2 ? s1 : real(0));   // node x - 1
-    const real sxp = x == 0 ? s1 : real(0);                     // node x + 1
-    lg_o[k] = lg[0] + sx;
-    if (hxm) lg_o[1 * P + k - 1] = lg[1] + sxm;
-    else {
-        lg_o[3 * P + k] = sx - lg[1];                           // Eq. 45, left wall
-        A.gthw[y] += A.cabb * double(lg[1]);
-    }
-    if (hxp) lg_o[3 * P + k + 1] = lg[3] + sxp;
-    else lg_o[1 * P + k] = sx - lg[3];                          // Eq. 45, right wall
-    if (hym) lg_o[2 * P + k - pitch] = lg[2] + sx; else lg_o[4 * P + k] = lg[2] + sx;
-    if (hyp) lg_o[4 * P + k + pitch] = lg[4] + sx; else lg_o[2 * P + k] = lg[4] + sx;
+    for (int i = 0; i < 5; ++i) A.lout[(9 + i) * P + k] = lg[i];
+    if (x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
 }
 
 template <typename real>
@@ -450,42 +470,37 @@ __global__ void __launch_bounds__(1024) adj_fused_kernel(AdjArgs<real> A, StepAr
     node_update<real, BC_CAVITY>(R.fin, R.gin, R.fout, R.gout, R.thw, R.n, R.pitch, R.plane, x, y, R.c);
 }
 
-// lambda(N) = dJ/ds(N): zero except the temperature seed next to the hot wall.
+// mu(N+1) = 0: the first adjoint step then forms lambda(N) = dJ/ds(N).
 template <typename real>
-__global__ void adj_seed_kernel(real* __restrict__ lam, int n, int pitch, int plane, real seed0,
-                                real seed1)
+__global__ void adj_zero_kernel(real* __restrict__ mu, int n, int pitch, int plane)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= n || y >= n) return;
     const int k = y * pitch + x;
-    const real s = x == 0 ? seed0 : (x == 1 ? seed1 : real(0));
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lam[i * plane + k] = real(0);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) lam[(9 + i) * plane + k] = s;
+    for (int i = 0; i < 14; ++i) mu[i * plane + k] = real(0);
 }
 
-// dJ/dtheta0 from lambda(0): the initial pre-collision state is f = 0,
-// g_i = w_i theta0, so dJ/dtheta0 = sum_i w_i (C'(p(0))^T lambda(0))_g,i.
+// dJ/dtheta0 from mu(1): lambda(0) = S^T mu(1) + dJ/ds(0); the initial
+// pre-collision state is f = 0, g_i = w_i theta0, so
+// dJ/dtheta0 = sum_i w_i (C'(p(0))^T lambda(0))_g,i.
 template <typename real>
-__global__ void adj_init_grad_kernel(const real* __restrict__ lam, const double* __restrict__ theta0,
+__global__ void adj_init_grad_kernel(const real* __restrict__ mu, const double* __restrict__ theta0,
                                      int n, int pitch, int plane, Coef<real> c, real w0, real wm,
-                                     double* __restrict__ grad)
+                                     bool win0, real seed0, real seed1, double* __restrict__ grad)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= n || y >= n) return;
-    const int k = y * pitch + x;
     const real th = real(theta0[y * n + x]);
     real f[9], g[5], lf[9], lg[5];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) { f[i] = real(0); lf[i] = lam[i * plane + k]; }
+    for (int i = 0; i < 9; ++i) f[i] = real(0);
     g[0] = w0 * th;
 #pragma unroll
     for (int i = 1; i < 5; ++i) g[i] = wm * th;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) lg[i] = lam[(9 + i) * plane + k];
+    adj_pull<real>(mu, n, pitch, plane, x, y, adj_seed_at<real>(x, win0, seed0, seed1), lf, lg);
     collide_vjp<real>(f, g, c, lf, lg);
     grad[y * n + x] = double(w0) * double(lg[0]) +
                       double(wm) * (double(lg[1]) + double(lg[2]) + double(lg[3]) + double(lg[4]));
@@ -509,19 +524,18 @@ static __global__ void __launch_bounds__(256) sum_kernel(const double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Two time steps per launch through LDS (temporal blocking), cavity walls.
+// Several time steps per launch through LDS (temporal blocking), cavity walls.
 // ---------------------------------------------------------------------------
-// Workgroup of 64 x R threads; its footprint is 64 x R nodes starting one
-// node left of and below its output tile of 62 x (R - 2) nodes.  Phase 1:
-// every thread computes s(t+1) at its footprint node from s(t) in global
-// memory (the ordinary gather + collide) into LDS.  Phase 2: the inner
-// threads compute s(t+2) at the output nodes, gathering s(t+1) from LDS with
-// the same wall rules, and store it.  Each output node's neighbours lie in
-// the footprint, so the two steps equal two single-step launches exactly.
-// Global traffic per node update: (64 R / (62 (R - 2)) + 1) * 14 / 2 words
-// instead of 28.
+// Workgroup of 64 x R threads; its footprint is 64 x R nodes starting K - 1
+// nodes left of and below its output tile.  Phase 1: every thread computes
+// s(t+1) at its footprint node from s(t) in global memory (the ordinary
+// gather + collide) into LDS.  Later phases compute the next step on a
+// footprint shrunk by one node per side, gathering from LDS with the same
+// wall rules; the last one stores to global memory.  Each node's neighbours
+// lie in the previous phase's region, so the K steps equal K single-step
+// launches exactly.  Global traffic per node update: about 28 / K words
+// instead of 28 (the footprint ring's re-reads hit L2).
 constexpr int kT2Width = 64;         // footprint width (one wavefront)
-constexpr int kT2Out = kT2Width - 2;  // output width of the two-step kernel
 
 template <typename real, int R>
 __device__ __forceinline__ real t2_lds(const real* lds, int q, int ly, int lx)
@@ -591,23 +605,39 @@ __device__ __forceinline__ void t2_phase2(const real* lds, real* __restrict__ fo
 // (R - 2(K-1)) nodes; phase j computes step t + j on the footprint shrunk by
 // j - 1 nodes on each side (phase 1 from HBM, the others from LDS; the
 // intermediate phases hold their result in registers across a barrier and
-// then overwrite the LDS copy), and the last phase stores to HBM.
-template <typename real, int R, int K>
-__global__ void __launch_bounds__(kT2Width * R) stepk_kernel(StepArgs<real> A)
+// then overwrite the LDS copy), and the last phase stores to HBM.  With ALL,
+// every intermediate state is also stored on the output tile (a partition
+// of the domain), state t + j at fout/gout + (j - 1) * slot: the adjoint's
+// recompute keeps every state of a segment.
+template <typename real, int R, int K, bool ALL>
+__device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, int tile, long slot)
 {
-    __shared__ real lds[14 * R * kT2Width];
     constexpr int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
     static_assert(W > 0 && HO > 0, "tile too small for K steps");
-    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
-    if (tile >= A.tiles) return;                      // uniform per workgroup
     const int tyt = tile / A.tiles_x;
     const int txt = tile - tyt * A.tiles_x;
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int x = txt * W - (K - 1) + lx;
     const int y = tyt * HO - (K - 1) + ly;
-    const int n = A.n;
+    const int n = A.n, P = A.plane, k = y * A.pitch + x;
     const bool inside = x >= 0 && x < n && y >= 0 && y < n;
-    if (inside) t2_phase1<real, R>(lds, A.fin, A.gin, A.thw, n, A.pitch, A.plane, x, y, lx, ly, A.c);
+    const bool own = inside && lx >= K - 1 && lx <= kT2Width - K && ly >= K - 1 && ly <= R - K;
+    if (inside) {
+        real f[9], g[5];
+        gather<real, BC_CAVITY>(A.fin, A.gin, A.thw, n, A.pitch, P, x, y, A.c, f, g);
+        real th, ux, uy;
+        collide<real>(f, g, A.c, th, ux, uy);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+        if (ALL && own) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) A.fout[i * P + k] = f[i];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) A.gout[i * P + k] = g[i];
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int j = 2; j < K; ++j) {
@@ -624,11 +654,147 @@ __global__ void __launch_bounds__(kT2Width * R) stepk_kernel(StepArgs<real> A)
             for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
 #pragma unroll
             for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+            if (ALL && own) {
+                real* fo = A.fout + (j - 1) * slot;
+                real* go = A.gout + (j - 1) * slot;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) fo[i * P + k] = f[i];
+#pragma unroll
+                for (int i = 0; i < 5; ++i) go[i * P + k] = g[i];
+            }
         }
         __syncthreads();
     }
-    if (!inside || lx < K - 1 || lx > kT2Width - K || ly < K - 1 || ly > R - K) return;
-    t2_phase2<real, R>(lds, A.fout, A.gout, A.thw, n, A.pitch, A.plane, x, y, lx, ly, A.c);
+    if (!own) return;
+    const long last = ALL ? (K - 1) * slot : 0;
+    t2_phase2<real, R>(lds, A.fout + last, A.gout + last, A.thw, n, A.pitch, P, x, y, lx, ly, A.c);
+}
+
+template <typename real, int R, int K>
+__global__ void __launch_bounds__(kT2Width * R) stepk_kernel(StepArgs<real> A)
+{
+    __shared__ real lds[14 * R * kT2Width];
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;                      // uniform per workgroup
+    stepk_tile<real, R, K, false>(A, lds, tile, 0);
+}
+
+// K forward steps storing every state (the adjoint's recompute on its own).
+template <typename real, int R, int K>
+__global__ void __launch_bounds__(kT2Width * R) stepk_all_kernel(StepArgs<real> A, long slot)
+{
+    __shared__ real lds[14 * R * kT2Width];
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;
+    stepk_tile<real, R, K, true>(A, lds, tile, slot);
+}
+
+// lambda at footprint node (lx, ly) from mu of the previous phase in LDS.
+template <typename real, int R>
+__device__ __forceinline__ void adj_pull_lds(const real* lds, int n, int x, int y, int lx, int ly,
+                                             real sd, real (&lf)[9], real (&lg)[5])
+{
+    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
+    lf[0] = t2_lds<real, R>(lds, 0, ly, lx);
+    lf[1] = hxp ? t2_lds<real, R>(lds, 1, ly, lx + 1) : t2_lds<real, R>(lds, 3, ly, lx);
+    lf[2] = hyp ? t2_lds<real, R>(lds, 2, ly + 1, lx) : t2_lds<real, R>(lds, 4, ly, lx);
+    lf[3] = hxm ? t2_lds<real, R>(lds, 3, ly, lx - 1) : t2_lds<real, R>(lds, 1, ly, lx);
+    lf[4] = hym ? t2_lds<real, R>(lds, 4, ly - 1, lx) : t2_lds<real, R>(lds, 2, ly, lx);
+    lf[5] = (hxp && hyp) ? t2_lds<real, R>(lds, 5, ly + 1, lx + 1) : t2_lds<real, R>(lds, 7, ly, lx);
+    lf[6] = (hxm && hyp) ? t2_lds<real, R>(lds, 6, ly + 1, lx - 1) : t2_lds<real, R>(lds, 8, ly, lx);
+    lf[7] = (hxm && hym) ? t2_lds<real, R>(lds, 7, ly - 1, lx - 1) : t2_lds<real, R>(lds, 5, ly, lx);
+    lf[8] = (hxp && hym) ? t2_lds<real, R>(lds, 8, ly - 1, lx + 1) : t2_lds<real, R>(lds, 6, ly, lx);
+    lg[0] = t2_lds<real, R>(lds, 9, ly, lx) + sd;
+    lg[1] = hxp ? t2_lds<real, R>(lds, 10, ly, lx + 1) + sd : sd - t2_lds<real, R>(lds, 12, ly, lx);
+    lg[2] = hyp ? t2_lds<real, R>(lds, 11, ly + 1, lx) + sd : t2_lds<real, R>(lds, 13, ly, lx) + sd;
+    lg[3] = hxm ? t2_lds<real, R>(lds, 12, ly, lx - 1) + sd : sd - t2_lds<real, R>(lds, 10, ly, lx);
+    lg[4] = hym ? t2_lds<real, R>(lds, 13, ly - 1, lx) + sd : t2_lds<real, R>(lds, 11, ly, lx) + sd;
+}
+
+// K adjoint steps per launch (m = *n0p + j down to m - K + 1): the mirror
+// image of stepk_tile.  Phase 1 pulls mu(m+1) from HBM on the footprint and
+// forms mu(m) into LDS; phase i pulls mu(m-i+2) from LDS on the footprint
+// shrunk by i - 1 nodes per side and forms mu(m-i+1), the state s(m-i)
+// coming from segment slot j - i (HBM); the last phase stores mu(m-K+1) on
+// the output tile.  Only output-tile nodes add to dJ/dtheta_w, in the same
+// order as single steps, so the result equals K single-step launches.
+template <typename real, int R, int K>
+__device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int tile)
+{
+    constexpr int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
+    static_assert(W > 0 && HO > 0, "tile too small for K steps");
+    const int tyt = tile / A.tiles_x;
+    const int txt = tile - tyt * A.tiles_x;
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int x = txt * W - (K - 1) + lx;
+    const int y = tyt * HO - (K - 1) + ly;
+    const int n = A.n, P = A.plane;
+    const bool inside = x >= 0 && x < n && y >= 0 && y < n;
+    const bool own = inside && lx >= K - 1 && lx <= kT2Width - K && ly >= K - 1 && ly <= R - K;
+    const int m = *A.n0p + A.j;
+    real lf[9], lg[5];
+    if (inside) {
+        adj_pull<real>(A.lin, n, A.pitch, P, x, y, adj_seed_at<real>(x, m >= A.win_start, A.seed0, A.seed1),
+                       lf, lg);
+        adj_node<real>(A.fs, A.gs, A, x, y, lf, lg);
+        if (own && x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = lf[i];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = lg[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 2; j <= K; ++j) {
+        const bool act = inside && lx >= j - 1 && lx <= kT2Width - j && ly >= j - 1 && ly <= R - j;
+        if (act) {
+            const int mj = m - j + 1;
+            adj_pull_lds<real, R>(lds, n, x, y, lx, ly,
+                                  adj_seed_at<real>(x, mj >= A.win_start, A.seed0, A.seed1), lf, lg);
+            adj_node<real>(A.fs - (j - 1) * A.slot, A.gs - (j - 1) * A.slot, A, x, y, lf, lg);
+            if (own && x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
+        }
+        if (j == K) break;
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = lf[i];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = lg[i];
+        }
+        __syncthreads();
+    }
+    if (!own) return;
+    const int k = y * A.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) A.lout[i * P + k] = lf[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) A.lout[(9 + i) * P + k] = lg[i];
+}
+
+template <typename real, int R, int K>
+__global__ void __launch_bounds__(kT2Width * R) adjk_kernel(AdjArgs<real> A)
+{
+    __shared__ real lds[14 * R * kT2Width];
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;
+    adjk_tile<real, R, K>(A, lds, tile);
+}
+
+// K adjoint steps of the current segment and K recompute steps of the
+// next-older one (every state stored) in one launch: workgroups
+// [0, A.tiles) take adjoint tiles, the rest forward tiles.
+template <typename real, int R, int K>
+__global__ void __launch_bounds__(kT2Width * R) adjk_fused_kernel(AdjArgs<real> A, StepArgs<real> F)
+{
+    __shared__ real lds[14 * R * kT2Width];
+    const int b = blockIdx.x;
+    if (b < A.tiles) {
+        adjk_tile<real, R, K>(A, lds, b);
+        return;
+    }
+    if (b - A.tiles >= F.tiles) return;
+    stepk_tile<real, R, K, true>(F, lds, b - A.tiles, A.slot);
 }
 
 // ---------------------------------------------------------------------------

@@ -75,7 +75,8 @@ struct dmrt_cavity {
     int series_stride = 0;
     // launch
     int block_x = 256, block_y = 1, xcd_remap = 1, graph_steps = 64;
-    int temporal = 1, t_rows = 10;    // steps per launch (1, or 2 through LDS) and its tile rows
+    int temporal = 1, t_rows = 10;    // steps per launch (1, or 2..4 through LDS) and its tile rows
+    int adj_temporal = 1, adj_rows = 10;   // the same for the adjoint's backward launches
     int graph_flips[2] = {0, 0};      // copy changes made by one replay of graph[p]
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipGraph_t graph_def[2] = {nullptr, nullptr};

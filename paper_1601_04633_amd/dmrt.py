@@ -101,6 +101,7 @@ _SIGS = {
     "dmrt_adjoint_backward": [_vp, _dp, _dp],
     "dmrt_adjoint_nu": [_vp, _c_long, _c_long, _c_long, _dp, _dp, _dp],
     "dmrt_adjoint_release": [_vp],
+    "dmrt_adjoint_set_temporal": [_vp, _c_int, _c_int],
     "dmrt_batch_create": [_P, _c_int, _vp, ctypes.POINTER(_vp)],
     "dmrt_batch_set_theta": [_vp, _c_int, _dp],
     "dmrt_batch_set_hot_wall": [_vp, _c_int, _dp],
@@ -333,6 +334,10 @@ class Cavity:
 
     def adjoint_release(self):
         check(dmrt_adjoint_release(self._h), "dmrt_adjoint_release")
+
+    def adjoint_set_temporal(self, steps_per_launch=2, tile_rows=10):
+        check(dmrt_adjoint_set_temporal(self._h, steps_per_launch, tile_rows),
+              "dmrt_adjoint_set_temporal")
 
     def set_temporal(self, steps_per_launch=2, tile_rows=10):
         check(dmrt_set_temporal(self._h, steps_per_launch, tile_rows), "dmrt_set_temporal")

@@ -177,3 +177,44 @@ def test_two_step_forward_does_not_change_gradients():
     for o in out[1:]:
         assert o[0] == out[0][0]
         assert np.array_equal(o[1], out[0][1]) and np.array_equal(o[2], out[0][2])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_multi_step_backward_does_not_change_gradients(precision):
+    """The backward may take K adjoint (and recompute) steps per launch
+    through LDS; the gradients are bitwise those of single-step launches,
+    also when the segment lengths are not multiples of K and when the
+    objective window starts inside a K-step launch."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    n, N, K, C = 70, 431, 149, 64
+    tw = inputs.hot_wall_profile(n, 31)
+    t0 = inputs.theta_noise(n, 32, amp=1e-2)
+    out = []
+    for temporal in ((1, 10), (2, 6), (2, 16), (3, 10), (3, 16), (4, 16)):
+        print(f"[adjoint] backward steps/launch, rows {temporal} {precision}", flush=True)
+        c = Cavity(n=n, Ra=1e4, Pr=0.01, precision=precision)
+        c.adjoint_set_temporal(*temporal)
+        c.set_hot_wall(tw)
+        c.set_theta(t0)
+        out.append(c.adjoint_nu(N, K, C))
+        c.close()
+    for o in out[1:]:
+        assert o[0] == out[0][0]
+        assert np.array_equal(o[1], out[0][1]) and np.array_equal(o[2], out[0][2])
+
+
+def test_multi_step_backward_against_reference():
+    """K steps per backward launch against the CPU reference gradient."""
+    from oracle.torch_ref import Reference
+    n, N, K, C = 32, 600, 150, 100
+    tw = inputs.hot_wall_profile(n, 23)
+    t0 = inputs.theta_noise(n, 24, amp=1e-2)
+    c = _cavity(n, 1e4, 0.01)
+    c.adjoint_set_temporal(3, 10)
+    c.set_hot_wall(tw)
+    c.set_theta(t0)
+    Jg, gw, g0 = c.adjoint_nu(N, K, C)
+    c.close()
+    Jr, rw, r0 = Reference(n, 1e4, 0.01).gradient(tw, t0, N, K, segment=100)
+    assert abs(Jg - Jr) <= 1e-12 * abs(Jr)
+    assert rel(gw, rw) <= 1e-10 and rel(g0, r0) <= 1e-10
