@@ -82,7 +82,8 @@ extern "C" {
 #define DMRT_BC_ADIABATIC_BOX 3
 
 typedef struct {
-    int    n;               /* nodes per side, >= 4                                */
+    int    n;               /* nodes per side, >= 4; 14 planes of the state must  *
+                             * stay under 4 GiB: n <= 8747 (FP32), 6177 (FP64)     */
     double Ra, Pr, Ma;      /* Eq. 9; all > 0                                      */
     double theta_hot;       /* hot-wall temperature (default +0.5)                 */
     double theta_cold;      /* cold-wall temperature (default -0.5)                */
@@ -91,7 +92,8 @@ typedef struct {
     double a;               /* D2Q5 parameter a of Eq. 42 in FIXED_A mode (-2/3)   */
     int    bc_mode;         /* DMRT_BC_*                                           */
     double gbeta_override;  /* NaN: g beta = Ma^2 / (3 H dT) from Eq. 9; else used */
-    double force_x;         /* constant horizontal body force (test boxes), 0      */
+    double force_x;         /* constant horizontal body force (test modes only;    *
+                             * DMRT_BC_CAVITY requires 0, else EINVAL), 0          */
     double theta_ref;       /* reference temperature of Eq. 27 (default 0)         */
 } dmrt_params;
 
@@ -115,8 +117,9 @@ int dmrt_params_default(dmrt_params *p);
 /* Parameter map of Eq. 9 / Eqs. 11-13 (H = n, c_s^2 = 1/3):
  *   nu = Ma H sqrt(Pr / (3 Ra)), alpha = nu / Pr, g beta = Ma^2 / (3 H dT);
  * Eq. 32 for s_nu, s_q; Eqs. 39-43 for sigma_k, sigma_e, sigma_nu and a.
- * Host only, touches no device.  DMRT_EINVAL for NULL or non-finite input or
- * n < 4; DMRT_EUNSTABLE for Ma, Ra or Pr <= 0, a outside (-4, 1), or any
+ * Host only, touches no device.  DMRT_EINVAL for NULL or non-finite input,
+ * n < 4 or n above the size limit of dmrt_params.n, or a horizontal force
+ * in the cavity; DMRT_EUNSTABLE for Ma, Ra or Pr <= 0, a outside (-4, 1), or any
  * relaxation rate outside (0, 2). */
 int dmrt_derive(const dmrt_params *p, dmrt_derived *out);
 

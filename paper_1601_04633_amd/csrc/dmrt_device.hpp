@@ -17,7 +17,17 @@
 
 #include <hip/hip_runtime.h>
 
+// Every multiply-add below is written out (fmr); nothing is contracted by
+// the compiler, so the arithmetic of a node update is the same in every
+// kernel it is inlined into and results do not depend on the launch shape
+// or on the number of steps per launch.
+#pragma clang fp contract(off)
+
 namespace dmrt {
+
+// a * b + c with one rounding.
+__host__ __device__ __forceinline__ float fmr(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmr(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 enum Bc { BC_CAVITY = 0, BC_PERIODIC = 1, BC_CHANNEL_X = 2, BC_ADIABATIC_BOX = 3 };
 
@@ -31,6 +41,11 @@ struct Coef {
     real gbeta, gy0;     // Eq. 27: G_y = gbeta theta + gy0, gy0 = -gbeta theta_ref
     real gx;             // constant horizontal force (test boxes)
     real cold;           // cabb * theta_cold
+    // relaxation rates divided by the squared norms of their rows of M
+    // (Eq. 30) and N (Eq. 37), negated: the moment changes come out
+    // already scaled for the inverse transform
+    real nsn36, nsn4, nsq12;   // -s_nu/36, -s_nu/4, -s_q/12
+    real nsk2, nse20, nsg4;    // -sigma_k/2, -sigma_e/20, -sigma_nu/4
 };
 
 // Sum over a 64-wide wavefront (FP64).
@@ -42,85 +57,114 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // Pre-collision populations in, post-collision populations out (Eq. 25 and
-// Eq. 36 right-hand sides).  Moments of Eq. 30 and Eq. 37 are expanded into
-// the +-1/+-2/+-4 adds the matrices encode; the inverse transforms use
+// Eq. 36 right-hand sides).  The moments of Eq. 30 and Eq. 37 are expanded
+// into the +-1/+-2/+-4 sums the matrices encode; the inverse transforms use
 // M^-1 = M^T diag(1/9, 1/6, 1/6, 1/36, 1/4, 1/4, 1/12, 1/12, 1/36) and
 // N^-1 = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4) (both matrices have orthogonal
-// rows).  Only the moment changes are transformed back.
-template <typename real>
+// rows), and only the moment changes are transformed back.  Moment order:
+// 1 j_x, 2 j_y, 3 e, 4 p_xx, 5 p_xy, 6 q_x, 7 q_y, 8 epsilon.  With GX false
+// the horizontal force is zero (the cavity, G = (0, G_y) of Eq. 27) and its
+// terms are left out.
+template <typename real, bool GX = false>
 __device__ __forceinline__ void collide(real (&f)[9], real (&g)[5], const Coef<real>& c,
                                         real& theta_out, real& ux_out, real& uy_out)
 {
-    const real one = real(1), two = real(2), three = real(3);
+    const real two = real(2), four = real(4);
     // Eq. 33, Eq. 41
-    const real s1234 = (f[1] + f[3]) + (f[2] + f[4]);
-    const real s5678 = (f[5] + f[7]) + (f[6] + f[8]);
-    const real drho = f[0] + s1234 + s5678;
-    const real u = (f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6]);
-    const real v = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
-    const real theta = g[0] + (g[1] + g[3]) + (g[2] + g[4]);
+    const real p13 = f[1] + f[3], p24 = f[2] + f[4], p57 = f[5] + f[7], p68 = f[6] + f[8];
+    const real d13 = f[1] - f[3], d24 = f[2] - f[4], d57 = f[5] - f[7], d86 = f[8] - f[6];
+    const real s1234 = p13 + p24, s5678 = p57 + p68;
+    const real drho = (f[0] + s1234) + s5678;
+    const real w = d57 + d86, z = d57 - d86;
+    const real u = d13 + w, v = d24 + z;
+    const real g13 = g[1] + g[3], g24 = g[2] + g[4];
+    const real gs = g13 + g24;
+    const real theta = g[0] + gs;
 
-    // non-conserved moments, rows 4-9 of Eq. 30
-    const real m3 = two * s5678 - s1234 - real(4) * f[0];
-    const real m4 = (f[1] + f[3]) - (f[2] + f[4]);
-    const real m5 = (f[5] + f[7]) - (f[6] + f[8]);
-    const real m6 = two * (f[3] - f[1]) + (f[5] - f[7]) + (f[8] - f[6]);
-    const real m7 = two * (f[4] - f[2]) + (f[5] - f[7]) + (f[6] - f[8]);
-    const real m8 = real(4) * f[0] - two * s1234 + s5678;
+    // non-conserved moments, rows 3-8 of Eq. 30
+    const real m3 = fmr(-four, f[0], fmr(two, s5678, -s1234));
+    const real m4 = p13 - p24;
+    const real m5 = p57 - p68;
+    const real m6 = fmr(-two, d13, w);
+    const real m7 = fmr(-two, d24, z);
+    const real m8 = fmr(four, f[0], fmr(-two, s1234, s5678));
 
-    // equilibria, Eq. 34 (energy moment with the factor 3)
-    const real uu = u * u, vv = v * v, q2 = uu + vv;
-    const real e3 = three * q2 - two * drho;
-    const real e4 = uu - vv;
-    const real e5 = u * v;
-    const real e8 = drho - three * q2;
+    // distance from the equilibria of Eq. 34 (energy moment with the
+    // factor 3): e3 = 3|u|^2 - 2 drho, e4 = u^2 - v^2, e5 = uv,
+    // e6 = -u, e7 = -v, e8 = drho - 3|u|^2
+    const real uu = u * u, vv = v * v, uv = u * v;
+    const real q2 = uu + vv, e4 = uu - vv;
+    const real r3 = fmr(two, drho, fmr(real(-3), q2, m3));
+    const real r8 = fmr(real(3), q2, m8 - drho);
+    const real r4 = m4 - e4, r5 = m5 - uv, r6 = m6 + u, r7 = m7 + v;
 
-    // moment image of the force of Eq. 26 with G = (gx, gbeta theta + gy0):
-    // the moments of 3 G.(e_i - u) w_i (1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u^2)
-    const real Gx = c.gx;
-    const real Gy = c.gbeta * theta + c.gy0;
-    const real F3 = three * (Gx * u + Gy * v) * (two - three * q2);
-    const real F4 = Gx * u * (two - three * uu + three * vv) - Gy * v * (two + three * uu - three * vv);
-    const real F5 = Gx * v * (one - three * uu) + Gy * u * (one - three * vv);
-    const real F6 = real(6) * Gy * u * v - Gx * (one - three * vv);
-    const real F7 = real(6) * Gx * u * v - Gy * (one - three * uu);
+    // moment image of the force of Eq. 26, 3 G.(e_i - u) f_i^eq(rho0, u),
+    // divided by the squared row norms: with G = (Gx, Gy)
+    //   F3 = 3 (G.u)(2 - 3|u|^2)                    F8 = -F3
+    //   F4 = Gx u (2 - 3u^2 + 3v^2) - Gy v (2 + 3u^2 - 3v^2)
+    //   F5 = Gx v (1 - 3u^2) + Gy u (1 - 3v^2)
+    //   F6 = 6 Gy uv - Gx (1 - 3v^2)                F7 = 6 Gx uv - Gy (1 - 3u^2)
+    const real Gy = fmr(c.gbeta, theta, c.gy0);
+    const real Gv = Gy * v, Gu = Gy * u;
+    const real h3 = fmr(real(-0.25), q2, real(1.0 / 6.0));
+    const real hq = real(0.5) * uv;
+    real F3, F4, F5, F6, F7, a1;
+    if constexpr (GX) {
+        const real Gx = c.gx;
+        F3 = fmr(Gx, u, Gv) * h3;
+        F4 = fmr(Gx * u, fmr(real(-0.75), e4, real(0.5)), Gv * fmr(real(-0.75), e4, real(-0.5)));
+        F5 = fmr(Gx * v, fmr(real(-0.75), uu, real(0.25)), Gu * fmr(real(-0.75), vv, real(0.25)));
+        F6 = fmr(Gx, fmr(real(0.25), vv, real(-1.0 / 12.0)), Gy * hq);
+        F7 = fmr(Gx, hq, Gy * fmr(real(0.25), uu, real(-1.0 / 12.0)));
+        a1 = Gx * real(1.0 / 6.0);
+    } else {
+        F3 = Gv * h3;
+        F4 = Gv * fmr(real(-0.75), e4, real(-0.5));
+        F5 = Gu * fmr(real(-0.75), vv, real(0.25));
+        F6 = Gy * hq;
+        F7 = Gy * fmr(real(0.25), uu, real(-1.0 / 12.0));
+        a1 = real(0);
+    }
 
-    // moment changes: -S (m - m_eq) + F   (Eq. 28, Eq. 31)
-    const real a1 = Gx * real(1.0 / 6.0);
+    // scaled moment changes -S (m - m_eq) + F   (Eq. 28, Eq. 31)
     const real a2 = Gy * real(1.0 / 6.0);
-    const real a3 = (F3 - c.s_nu * (m3 - e3)) * real(1.0 / 36.0);
-    const real a4 = (F4 - c.s_nu * (m4 - e4)) * real(0.25);
-    const real a5 = (F5 - c.s_nu * (m5 - e5)) * real(0.25);
-    const real a6 = (F6 - c.s_q * (m6 + u)) * real(1.0 / 12.0);
-    const real a7 = (F7 - c.s_q * (m7 + v)) * real(1.0 / 12.0);
-    const real a8 = (-F3 - c.s_nu * (m8 - e8)) * real(1.0 / 36.0);
+    const real a3 = fmr(c.nsn36, r3, F3);
+    const real a8 = fmr(c.nsn36, r8, -F3);
+    const real a4 = fmr(c.nsn4, r4, F4);
+    const real a5 = fmr(c.nsn4, r5, F5);
+    const real a6 = fmr(c.nsq12, r6, F6);
+    const real a7 = fmr(c.nsq12, r7, F7);
 
     // f += M^T a
-    const real d2 = two * a3 + a8;              // shared by the four diagonals
-    f[0] += real(4) * (a8 - a3);
-    f[1] += a1 - a3 + a4 - two * a6 - two * a8;
-    f[2] += a2 - a3 - a4 - two * a7 - two * a8;
-    f[3] += -a1 - a3 + a4 + two * a6 - two * a8;
-    f[4] += -a2 - a3 - a4 + two * a7 - two * a8;
-    f[5] += d2 + (a1 + a2) + (a5 + a6 + a7);
-    f[6] += d2 + (a2 - a1) + (a7 - a5 - a6);
-    f[7] += d2 - (a1 + a2) + (a5 - a6 - a7);
-    f[8] += d2 + (a1 - a2) + (a6 - a5 - a7);
+    const real A = fmr(-two, a8, -a3);          // f1..f4: -a3 - 2 a8
+    const real D = fmr(two, a3, a8);            // f5..f8: 2 a3 + a8
+    const real P = A + a4, Q = A - a4;
+    const real U1 = GX ? fmr(-two, a6, a1) : -two * a6;
+    const real V1 = fmr(-two, a7, a2);
+    const real X = GX ? a1 + a6 : a6;
+    const real Y = a2 + a7;
+    const real S = X + Y, T = Y - X, Rp = D + a5, Rm = D - a5;
+    f[0] = fmr(four, a8 - a3, f[0]);
+    f[1] += P + U1;
+    f[3] += P - U1;
+    f[2] += Q + V1;
+    f[4] += Q - V1;
+    f[5] += Rp + S;
+    f[7] += Rp - S;
+    f[6] += Rm + T;
+    f[8] += Rm - T;
 
     // D2Q5, Eqs. 36-42 (last row of N read as e_x^2 - e_y^2)
-    const real n1 = g[1] - g[3];
-    const real n2 = g[2] - g[4];
-    const real n3 = (g[1] + g[3]) + (g[2] + g[4]) - real(4) * g[0];
-    const real n4 = (g[1] + g[3]) - (g[2] + g[4]);
-    const real b1 = -c.sk * (n1 - u * theta) * real(0.5);
-    const real b2 = -c.sk * (n2 - v * theta) * real(0.5);
-    const real b3 = -c.se * (n3 - c.a * theta) * real(0.05);
-    const real b4 = -c.sn * n4 * real(0.25);
-    g[0] += real(-4) * b3;
-    g[1] += b1 + b3 + b4;
-    g[2] += b2 + b3 - b4;
-    g[3] += b3 + b4 - b1;
-    g[4] += b3 - b4 - b2;
+    const real b1 = c.nsk2 * fmr(-u, theta, g[1] - g[3]);
+    const real b2 = c.nsk2 * fmr(-v, theta, g[2] - g[4]);
+    const real b3 = c.nse20 * fmr(-c.a, theta, fmr(-four, g[0], gs));
+    const real b4 = c.nsg4 * (g13 - g24);
+    const real t34 = b3 + b4, t34m = b3 - b4;
+    g[0] = fmr(-four, b3, g[0]);
+    g[1] += b1 + t34;
+    g[3] += t34 - b1;
+    g[2] += b2 + t34m;
+    g[4] += t34m - b2;
 
     theta_out = theta;
     ux_out = u;
@@ -158,11 +202,45 @@ __device__ __forceinline__ int tile_of_block(int bid, int nblocks, int remap)
 // Pull-streaming with the wall rules (row a1): f_i(r) = f*_i(r - e_i) when
 // r - e_i is inside, else the halfway bounce-back f*_opp(i)(r); for g the
 // same, with Eq. 44 on adiabatic walls and Eq. 45 on the isothermal walls.
+// Element at byte offset `b` from `base`: a uniform base pointer and a
+// 32-bit per-lane offset, so a load needs no 64-bit address arithmetic.
+template <typename real>
+__device__ __forceinline__ real ldb(const real* __restrict__ base, unsigned b)
+{
+    return *reinterpret_cast<const real*>(reinterpret_cast<const char*>(base) + b);
+}
+template <typename real>
+__device__ __forceinline__ void stb(real* __restrict__ base, unsigned b, real v)
+{
+    *reinterpret_cast<real*>(reinterpret_cast<char*>(base) + b) = v;
+}
+
 template <typename real, int BC>
 __device__ __forceinline__ void gather(const real* __restrict__ fi, const real* __restrict__ gi,
                                        const real* __restrict__ thw, int n, int pitch, int P,
                                        int x, int y, const Coef<real>& c, real (&f)[9], real (&g)[5])
 {
+    if constexpr (BC == BC_CAVITY) {
+        // every offset below is >= 0 (plane index >= 1 for the neighbour reads)
+        constexpr unsigned E = sizeof(real);
+        const unsigned kb = unsigned(y * pitch + x) * E, Pb = unsigned(P) * E, rb = unsigned(pitch) * E;
+        const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
+        f[0] = ldb(fi, kb);
+        f[1] = ldb(fi, hxm ? kb + Pb - E : kb + 3 * Pb);
+        f[2] = ldb(fi, hym ? kb + 2 * Pb - rb : kb + 4 * Pb);
+        f[3] = ldb(fi, hxp ? kb + 3 * Pb + E : kb + Pb);
+        f[4] = ldb(fi, hyp ? kb + 4 * Pb + rb : kb + 2 * Pb);
+        f[5] = ldb(fi, (hxm && hym) ? kb + 5 * Pb - rb - E : kb + 7 * Pb);
+        f[6] = ldb(fi, (hxp && hym) ? kb + 6 * Pb - rb + E : kb + 8 * Pb);
+        f[7] = ldb(fi, (hxp && hyp) ? kb + 7 * Pb + rb + E : kb + 5 * Pb);
+        f[8] = ldb(fi, (hxm && hyp) ? kb + 8 * Pb + rb - E : kb + 6 * Pb);
+        g[0] = ldb(gi, kb);
+        g[2] = ldb(gi, hym ? kb + 2 * Pb - rb : kb + 4 * Pb);        // Eq. 44
+        g[4] = ldb(gi, hyp ? kb + 4 * Pb + rb : kb + 2 * Pb);
+        g[1] = hxm ? ldb(gi, kb + Pb - E) : fmr(c.cabb, thw[y], -ldb(gi, kb + 3 * Pb));   // Eq. 45
+        g[3] = hxp ? ldb(gi, kb + 3 * Pb + E) : c.cold - ldb(gi, kb + Pb);
+        return;
+    }
     constexpr bool PX = (BC == BC_PERIODIC || BC == BC_CHANNEL_X);
     constexpr bool PY = (BC == BC_PERIODIC);
     constexpr bool ABB = (BC == BC_CAVITY);
@@ -190,7 +268,7 @@ __device__ __forceinline__ void gather(const real* __restrict__ fi, const real* 
     g[2] = hym ? gi[2 * P + k + dym] : gi[4 * P + k];       // Eq. 44
     g[4] = hyp ? gi[4 * P + k + dyp] : gi[2 * P + k];
     if (ABB) {                                              // Eq. 45
-        g[1] = hxm ? gi[1 * P + k + dxm] : c.cabb * thw[y] - gi[3 * P + k];
+        g[1] = hxm ? gi[1 * P + k + dxm] : fmr(c.cabb, thw[y], -gi[3 * P + k]);
         g[3] = hxp ? gi[3 * P + k + dxp] : c.cold - gi[1 * P + k];
     } else {
         g[1] = hxm ? gi[1 * P + k + dxm] : gi[3 * P + k];
@@ -211,12 +289,12 @@ __device__ __forceinline__ double node_update(const real* __restrict__ fi, const
     real f[9], g[5];
     gather<real, BC>(fi, gi, thw, n, pitch, P, x, y, c, f, g);
     real th, ux, uy;
-    collide<real>(f, g, c, th, ux, uy);
-    const int k = y * pitch + x;
+    collide<real, BC != BC_CAVITY>(f, g, c, th, ux, uy);
+    const unsigned kb = unsigned(y * pitch + x) * sizeof(real), Pb = unsigned(P) * sizeof(real);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fo[i * P + k] = f[i];
+    for (int i = 0; i < 9; ++i) stb(fo, kb + i * Pb, f[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) go[i * P + k] = g[i];
+    for (int i = 0; i < 5; ++i) stb(go, kb + i * Pb, g[i]);
     double ts = 0.0;
 #pragma unroll
     for (int i = 0; i < 5; ++i) ts += double(g[i]);
@@ -273,10 +351,6 @@ template <typename real>
 __device__ __forceinline__ void collide_vjp(const real (&f)[9], const real (&g)[5], const Coef<real>& c,
                                             real (&lf)[9], real (&lg)[5])
 {
-    // No multiply-add contraction here: the compiler's choice would differ
-    // between the kernels this is inlined into, and the adjoint must give
-    // the same bits whatever the number of steps per launch.
-#pragma clang fp contract(off)
     const real two = real(2), three = real(3), six = real(6);
     const real u = (f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6]);
     const real v = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
@@ -383,23 +457,25 @@ template <typename real>
 __device__ __forceinline__ void adj_pull(const real* __restrict__ mu, int n, int pitch, int P, int x,
                                          int y, real sd, real (&lf)[9], real (&lg)[5])
 {
-    const int k = y * pitch + x;
+    // every offset below is >= 0 (plane index >= 1 for the neighbour reads)
+    constexpr unsigned E = sizeof(real);
+    const unsigned kb = unsigned(y * pitch + x) * E, Pb = unsigned(P) * E, rb = unsigned(pitch) * E;
     const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
-    lf[0] = mu[k];
-    lf[1] = hxp ? mu[1 * P + k + 1] : mu[3 * P + k];
-    lf[2] = hyp ? mu[2 * P + k + pitch] : mu[4 * P + k];
-    lf[3] = hxm ? mu[3 * P + k - 1] : mu[1 * P + k];
-    lf[4] = hym ? mu[4 * P + k - pitch] : mu[2 * P + k];
-    lf[5] = (hxp && hyp) ? mu[5 * P + k + pitch + 1] : mu[7 * P + k];
-    lf[6] = (hxm && hyp) ? mu[6 * P + k + pitch - 1] : mu[8 * P + k];
-    lf[7] = (hxm && hym) ? mu[7 * P + k - pitch - 1] : mu[5 * P + k];
-    lf[8] = (hxp && hym) ? mu[8 * P + k - pitch + 1] : mu[6 * P + k];
+    lf[0] = ldb(mu, kb);
+    lf[1] = ldb(mu, hxp ? kb + Pb + E : kb + 3 * Pb);
+    lf[2] = ldb(mu, hyp ? kb + 2 * Pb + rb : kb + 4 * Pb);
+    lf[3] = ldb(mu, hxm ? kb + 3 * Pb - E : kb + Pb);
+    lf[4] = ldb(mu, hym ? kb + 4 * Pb - rb : kb + 2 * Pb);
+    lf[5] = ldb(mu, (hxp && hyp) ? kb + 5 * Pb + rb + E : kb + 7 * Pb);
+    lf[6] = ldb(mu, (hxm && hyp) ? kb + 6 * Pb + rb - E : kb + 8 * Pb);
+    lf[7] = ldb(mu, (hxm && hym) ? kb + 7 * Pb - rb - E : kb + 5 * Pb);
+    lf[8] = ldb(mu, (hxp && hym) ? kb + 8 * Pb - rb + E : kb + 6 * Pb);
     const real* __restrict__ mg = mu + 9 * P;
-    lg[0] = mg[k] + sd;
-    lg[1] = hxp ? mg[1 * P + k + 1] + sd : sd - mg[3 * P + k];         // Eq. 45, right wall
-    lg[2] = hyp ? mg[2 * P + k + pitch] + sd : mg[4 * P + k] + sd;      // Eq. 44
-    lg[3] = hxm ? mg[3 * P + k - 1] + sd : sd - mg[1 * P + k];         // Eq. 45, left wall
-    lg[4] = hym ? mg[4 * P + k - pitch] + sd : mg[2 * P + k] + sd;
+    lg[0] = ldb(mg, kb) + sd;
+    lg[1] = hxp ? ldb(mg, kb + Pb + E) + sd : sd - ldb(mg, kb + 3 * Pb);           // Eq. 45, right wall
+    lg[2] = ldb(mg, hyp ? kb + 2 * Pb + rb : kb + 4 * Pb) + sd;                    // Eq. 44
+    lg[3] = hxm ? ldb(mg, kb + 3 * Pb - E) + sd : sd - ldb(mg, kb + Pb);           // Eq. 45, left wall
+    lg[4] = ldb(mg, hym ? kb + 4 * Pb - rb : kb + 2 * Pb) + sd;
 }
 
 // One adjoint node update: mu(m) = C'(p(m))^T lambda(m), with p(m) gathered
@@ -428,16 +504,17 @@ __device__ __forceinline__ void adj_tile(const AdjArgs<real>& A, int tile)
     const int y = ty * blockDim.y + threadIdx.y;
     const int n = A.n;
     if (x >= n || y >= n) return;
-    const int P = A.plane, k = y * A.pitch + x;
+    const int P = A.plane;
     const int m = *A.n0p + A.j;
     real lf[9], lg[5];
     adj_pull<real>(A.lin, n, A.pitch, P, x, y, adj_seed_at<real>(x, m >= A.win_start, A.seed0, A.seed1),
                    lf, lg);
     adj_node<real>(A.fs, A.gs, A, x, y, lf, lg);
+    const unsigned kb = unsigned(y * A.pitch + x) * sizeof(real), Pb = unsigned(P) * sizeof(real);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) A.lout[i * P + k] = lf[i];
+    for (int i = 0; i < 9; ++i) stb(A.lout, kb + i * Pb, lf[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) A.lout[(9 + i) * P + k] = lg[i];
+    for (int i = 0; i < 5; ++i) stb(A.lout, kb + (9 + i) * Pb, lg[i]);
     if (x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
 }
 
@@ -561,27 +638,42 @@ __device__ __forceinline__ void t2_phase1(real* lds, const real* __restrict__ fi
 }
 
 // Gather of s(t+j-1) for node (x, y) from LDS with the cavity's wall rules.
+// Every lane first reads the interior neighbours (one base address and
+// constant offsets, all inside the footprint for an active lane); lanes on
+// a wall then replace the links that cross it by the bounce-back values of
+// their own node.
 template <typename real, int R>
 __device__ __forceinline__ void t2_gather_lds(const real* lds, const real* __restrict__ thw, int n,
                                               int x, int y, int lx, int ly, const Coef<real>& c,
                                               real (&f)[9], real (&g)[5])
 {
+    constexpr int W = kT2Width, PL = R * kT2Width;
+    const real* b = lds + (ly * W + lx);
+    f[0] = b[0];
+    f[1] = b[1 * PL - 1];
+    f[2] = b[2 * PL - W];
+    f[3] = b[3 * PL + 1];
+    f[4] = b[4 * PL + W];
+    f[5] = b[5 * PL - W - 1];
+    f[6] = b[6 * PL - W + 1];
+    f[7] = b[7 * PL + W + 1];
+    f[8] = b[8 * PL + W - 1];
+    g[0] = b[9 * PL];
+    g[1] = b[10 * PL - 1];
+    g[2] = b[11 * PL - W];
+    g[3] = b[12 * PL + 1];
+    g[4] = b[13 * PL + W];
     const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
-    f[0] = t2_lds<real, R>(lds, 0, ly, lx);
-    f[1] = hxm ? t2_lds<real, R>(lds, 1, ly, lx - 1) : t2_lds<real, R>(lds, 3, ly, lx);
-    f[2] = hym ? t2_lds<real, R>(lds, 2, ly - 1, lx) : t2_lds<real, R>(lds, 4, ly, lx);
-    f[3] = hxp ? t2_lds<real, R>(lds, 3, ly, lx + 1) : t2_lds<real, R>(lds, 1, ly, lx);
-    f[4] = hyp ? t2_lds<real, R>(lds, 4, ly + 1, lx) : t2_lds<real, R>(lds, 2, ly, lx);
-    f[5] = (hxm && hym) ? t2_lds<real, R>(lds, 5, ly - 1, lx - 1) : t2_lds<real, R>(lds, 7, ly, lx);
-    f[6] = (hxp && hym) ? t2_lds<real, R>(lds, 6, ly - 1, lx + 1) : t2_lds<real, R>(lds, 8, ly, lx);
-    f[7] = (hxp && hyp) ? t2_lds<real, R>(lds, 7, ly + 1, lx + 1) : t2_lds<real, R>(lds, 5, ly, lx);
-    f[8] = (hxm && hyp) ? t2_lds<real, R>(lds, 8, ly + 1, lx - 1) : t2_lds<real, R>(lds, 6, ly, lx);
-    g[0] = t2_lds<real, R>(lds, 9, ly, lx);
-    g[2] = hym ? t2_lds<real, R>(lds, 11, ly - 1, lx) : t2_lds<real, R>(lds, 13, ly, lx);    // Eq. 44
-    g[4] = hyp ? t2_lds<real, R>(lds, 13, ly + 1, lx) : t2_lds<real, R>(lds, 11, ly, lx);
-    g[1] = hxm ? t2_lds<real, R>(lds, 10, ly, lx - 1)                                         // Eq. 45
-               : c.cabb * thw[y] - t2_lds<real, R>(lds, 12, ly, lx);
-    g[3] = hxp ? t2_lds<real, R>(lds, 12, ly, lx + 1) : c.cold - t2_lds<real, R>(lds, 10, ly, lx);
+    if (!(hxm && hxp && hym && hyp)) {
+        if (!hxm) { f[1] = b[3 * PL]; g[1] = fmr(c.cabb, thw[y], -b[12 * PL]); }   // Eq. 45
+        if (!hxp) { f[3] = b[1 * PL]; g[3] = c.cold - b[10 * PL]; }
+        if (!hym) { f[2] = b[4 * PL]; g[2] = b[13 * PL]; }                          // Eq. 44
+        if (!hyp) { f[4] = b[2 * PL]; g[4] = b[11 * PL]; }
+        if (!(hxm && hym)) f[5] = b[7 * PL];
+        if (!(hxp && hym)) f[6] = b[8 * PL];
+        if (!(hxp && hyp)) f[7] = b[5 * PL];
+        if (!(hxm && hyp)) f[8] = b[6 * PL];
+    }
 }
 
 // Last phase: the final step at output node (x, y) from LDS, stored to global.
@@ -594,11 +686,11 @@ __device__ __forceinline__ void t2_phase2(const real* lds, real* __restrict__ fo
     t2_gather_lds<real, R>(lds, thw, n, x, y, lx, ly, c, f, g);
     real th, ux, uy;
     collide<real>(f, g, c, th, ux, uy);
-    const int k = y * pitch + x;
+    const unsigned kb = unsigned(y * pitch + x) * sizeof(real), Pb = unsigned(P) * sizeof(real);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fo[i * P + k] = f[i];
+    for (int i = 0; i < 9; ++i) stb(fo, kb + i * Pb, f[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) go[i * P + k] = g[i];
+    for (int i = 0; i < 5; ++i) stb(go, kb + i * Pb, g[i]);
 }
 
 // K steps per launch.  Footprint 64 x R nodes, output (64 - 2(K-1)) x
@@ -622,8 +714,12 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
     const int n = A.n, P = A.plane, k = y * A.pitch + x;
     const bool inside = x >= 0 && x < n && y >= 0 && y < n;
     const bool own = inside && lx >= K - 1 && lx <= kT2Width - K && ly >= K - 1 && ly <= R - K;
+    real f[9], g[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = real(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) g[i] = real(0);
     if (inside) {
-        real f[9], g[5];
         gather<real, BC_CAVITY>(A.fin, A.gin, A.thw, n, A.pitch, P, x, y, A.c, f, g);
         real th, ux, uy;
         collide<real>(f, g, A.c, th, ux, uy);
@@ -642,7 +738,6 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
 #pragma unroll
     for (int j = 2; j < K; ++j) {
         const bool act = inside && lx >= j - 1 && lx <= kT2Width - j && ly >= j - 1 && ly <= R - j;
-        real f[9], g[5];
         if (act) {
             t2_gather_lds<real, R>(lds, A.thw, n, x, y, lx, ly, A.c, f, g);
             real th, ux, uy;
@@ -689,26 +784,40 @@ __global__ void __launch_bounds__(kT2Width * R) stepk_all_kernel(StepArgs<real> 
     stepk_tile<real, R, K, true>(A, lds, tile, slot);
 }
 
-// lambda at footprint node (lx, ly) from mu of the previous phase in LDS.
+// lambda at footprint node (lx, ly) from mu of the previous phase in LDS:
+// interior links first (one base address, constant offsets), then the wall
+// links of lanes on a wall.
 template <typename real, int R>
 __device__ __forceinline__ void adj_pull_lds(const real* lds, int n, int x, int y, int lx, int ly,
                                              real sd, real (&lf)[9], real (&lg)[5])
 {
+    constexpr int W = kT2Width, PL = R * kT2Width;
+    const real* b = lds + (ly * W + lx);
+    lf[0] = b[0];
+    lf[1] = b[1 * PL + 1];
+    lf[2] = b[2 * PL + W];
+    lf[3] = b[3 * PL - 1];
+    lf[4] = b[4 * PL - W];
+    lf[5] = b[5 * PL + W + 1];
+    lf[6] = b[6 * PL + W - 1];
+    lf[7] = b[7 * PL - W - 1];
+    lf[8] = b[8 * PL - W + 1];
+    lg[0] = b[9 * PL] + sd;
+    lg[1] = b[10 * PL + 1] + sd;
+    lg[2] = b[11 * PL + W] + sd;
+    lg[3] = b[12 * PL - 1] + sd;
+    lg[4] = b[13 * PL - W] + sd;
     const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
-    lf[0] = t2_lds<real, R>(lds, 0, ly, lx);
-    lf[1] = hxp ? t2_lds<real, R>(lds, 1, ly, lx + 1) : t2_lds<real, R>(lds, 3, ly, lx);
-    lf[2] = hyp ? t2_lds<real, R>(lds, 2, ly + 1, lx) : t2_lds<real, R>(lds, 4, ly, lx);
-    lf[3] = hxm ? t2_lds<real, R>(lds, 3, ly, lx - 1) : t2_lds<real, R>(lds, 1, ly, lx);
-    lf[4] = hym ? t2_lds<real, R>(lds, 4, ly - 1, lx) : t2_lds<real, R>(lds, 2, ly, lx);
-    lf[5] = (hxp && hyp) ? t2_lds<real, R>(lds, 5, ly + 1, lx + 1) : t2_lds<real, R>(lds, 7, ly, lx);
-    lf[6] = (hxm && hyp) ? t2_lds<real, R>(lds, 6, ly + 1, lx - 1) : t2_lds<real, R>(lds, 8, ly, lx);
-    lf[7] = (hxm && hym) ? t2_lds<real, R>(lds, 7, ly - 1, lx - 1) : t2_lds<real, R>(lds, 5, ly, lx);
-    lf[8] = (hxp && hym) ? t2_lds<real, R>(lds, 8, ly - 1, lx + 1) : t2_lds<real, R>(lds, 6, ly, lx);
-    lg[0] = t2_lds<real, R>(lds, 9, ly, lx) + sd;
-    lg[1] = hxp ? t2_lds<real, R>(lds, 10, ly, lx + 1) + sd : sd - t2_lds<real, R>(lds, 12, ly, lx);
-    lg[2] = hyp ? t2_lds<real, R>(lds, 11, ly + 1, lx) + sd : t2_lds<real, R>(lds, 13, ly, lx) + sd;
-    lg[3] = hxm ? t2_lds<real, R>(lds, 12, ly, lx - 1) + sd : sd - t2_lds<real, R>(lds, 10, ly, lx);
-    lg[4] = hym ? t2_lds<real, R>(lds, 13, ly - 1, lx) + sd : t2_lds<real, R>(lds, 11, ly, lx) + sd;
+    if (!(hxm && hxp && hym && hyp)) {
+        if (!hxp) { lf[1] = b[3 * PL]; lg[1] = sd - b[12 * PL]; }      // Eq. 45, right wall
+        if (!hxm) { lf[3] = b[1 * PL]; lg[3] = sd - b[10 * PL]; }      // Eq. 45, left wall
+        if (!hyp) { lf[2] = b[4 * PL]; lg[2] = b[13 * PL] + sd; }      // Eq. 44
+        if (!hym) { lf[4] = b[2 * PL]; lg[4] = b[11 * PL] + sd; }
+        if (!(hxp && hyp)) lf[5] = b[7 * PL];
+        if (!(hxm && hyp)) lf[6] = b[8 * PL];
+        if (!(hxm && hym)) lf[7] = b[5 * PL];
+        if (!(hxp && hym)) lf[8] = b[6 * PL];
+    }
 }
 
 // K adjoint steps per launch (m = *n0p + j down to m - K + 1): the mirror
@@ -733,6 +842,10 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
     const bool own = inside && lx >= K - 1 && lx <= kT2Width - K && ly >= K - 1 && ly <= R - K;
     const int m = *A.n0p + A.j;
     real lf[9], lg[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lf[i] = real(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) lg[i] = real(0);
     if (inside) {
         adj_pull<real>(A.lin, n, A.pitch, P, x, y, adj_seed_at<real>(x, m >= A.win_start, A.seed0, A.seed1),
                        lf, lg);
@@ -765,11 +878,11 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
         __syncthreads();
     }
     if (!own) return;
-    const int k = y * A.pitch + x;
+    const unsigned kb = unsigned(y * A.pitch + x) * sizeof(real), Pb = unsigned(P) * sizeof(real);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) A.lout[i * P + k] = lf[i];
+    for (int i = 0; i < 9; ++i) stb(A.lout, kb + i * Pb, lf[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) A.lout[(9 + i) * P + k] = lg[i];
+    for (int i = 0; i < 5; ++i) stb(A.lout, kb + (9 + i) * Pb, lg[i]);
 }
 
 template <typename real, int R, int K>
@@ -873,7 +986,7 @@ __global__ void init_kernel(real* __restrict__ fout, real* __restrict__ gout,
     for (int i = 1; i < 5; ++i)
         g[i] = wm * th + real(0.5) * th * (real(ex[i]) * u + real(ey[i]) * v);
     real a, b, d;
-    collide<real>(f, g, c, a, b, d);
+    collide<real, true>(f, g, c, a, b, d);
     const int k = y * pitch + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) fout[i * plane + k] = f[i];
@@ -989,10 +1102,14 @@ __global__ void __launch_bounds__(kT2Width * R) batch_stepk_kernel(
         if (inside)
             t2_phase1<real, R>(lds, cv.f[cur], cv.g[cur], cv.thw, n, cv.pitch, cv.plane, x, y, lx, ly, cv.c);
         __syncthreads();
+        real f[9], g[5];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = real(0);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[i] = real(0);
 #pragma unroll
         for (int j = 2; j < K; ++j) {
             const bool act = inside && lx >= j - 1 && lx <= kT2Width - j && ly >= j - 1 && ly <= R - j;
-            real f[9], g[5];
             if (act) {
                 t2_gather_lds<real, R>(lds, cv.thw, n, x, y, lx, ly, cv.c, f, g);
                 real th, ux, uy;

@@ -50,7 +50,11 @@ int derive(const dmrt_params* p, dmrt_derived* d)
     for (double v : vals)
         if (!std::isfinite(v)) return DMRT_EINVAL;
     if (p->precision != DMRT_FP32 && p->precision != DMRT_FP64) return DMRT_EINVAL;
+    // kernels address a 14-plane state with 32-bit byte offsets
+    const double esz = p->precision == DMRT_FP64 ? 8.0 : 4.0;
+    if (14.0 * esz * (double)((p->n + 63) / 64 * 64) * p->n >= 4294967296.0) return DMRT_EINVAL;
     if (p->bc_mode < DMRT_BC_CAVITY || p->bc_mode > DMRT_BC_ADIABATIC_BOX) return DMRT_EINVAL;
+    if (p->bc_mode == DMRT_BC_CAVITY && p->force_x != 0.0) return DMRT_EINVAL;   // G = (0, G_y)
     if (!(p->Ra > 0.0) || !(p->Pr > 0.0) || !(p->Ma > 0.0)) return DMRT_EUNSTABLE;
     const double H = p->n;
     const double dT = p->theta_hot - p->theta_cold;

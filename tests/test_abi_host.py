@@ -53,12 +53,21 @@ def test_derive_agrees_with_oracle(oracle_mod, n, Ra, Pr, mode, Ma, a):
     (dict(a=-4.0), "DMRT_EUNSTABLE"), (dict(precision=7), "DMRT_EINVAL"),
     (dict(bc_mode=9), "DMRT_EINVAL"), (dict(q5_mode=5), "DMRT_EINVAL"),
     (dict(theta_hot=-0.5), "DMRT_EINVAL"), (dict(force_x=float("inf")), "DMRT_EINVAL"),
+    (dict(force_x=1e-5), "DMRT_EINVAL"), (dict(n=8748, precision=0), "DMRT_EINVAL"),
+    (dict(n=6178, precision=1), "DMRT_EINVAL"),
     (dict(q5_mode=1), "DMRT_EUNSTABLE"),
 ])
 def test_derive_errors(kw, code):
     p = D.make_params(**kw)
     d = D.dmrt_derived()
     assert D.dmrt_derive(ctypes.byref(p), ctypes.byref(d)) == getattr(D, code)
+
+
+@pytest.mark.parametrize("n,prec", [(8747, 0), (6177, 1)])
+def test_largest_cavity_accepted(n, prec):
+    p = D.make_params(n=n, precision=prec)
+    d = D.dmrt_derived()
+    assert D.dmrt_derive(ctypes.byref(p), ctypes.byref(d)) == D.DMRT_OK
 
 
 def test_derive_null():
