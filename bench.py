@@ -32,13 +32,13 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD published)
 WORDS_PER_NODE = 28            # 14 populations read + 14 written per node update
 TRAFFIC_FILES = {
     "step_kernel<float, 0>": os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json"),
-    "stepk_kernel<float, 16, 3>": os.path.join(ROOT, "profiles",
-                                               "stepk_kernel_K3_R16_cavity_1024_fp32_traffic.json"),
+    "stepk_kernel<float, 16, 4>": os.path.join(ROOT, "profiles",
+                                               "stepk_kernel_K4_R16_cavity_1024_fp32_traffic.json"),
 }
 # launch configuration timed by default (the fastest for this workload on
-# MI355X): three steps per launch through LDS, 64 x 16 footprints,
+# MI355X): four steps per launch through LDS, 64 x 16 footprints,
 # die-aware tile order, graphs of 60 steps
-DEFAULT_TEMPORAL = (3, 16)
+DEFAULT_TEMPORAL = (4, 16)
 DEFAULT_LAUNCH = (256, 1, 1, 60)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_04633_amd", "csrc", f)
                   for f in ("dmrt_device.hpp",)]
@@ -254,7 +254,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,xcd_remap,graph_steps")
-    ap.add_argument("--temporal", default="", help="steps_per_launch,tile_rows (default 3,16)")
+    ap.add_argument("--temporal", default="", help="steps_per_launch,tile_rows (default 4,16)")
     ap.add_argument("--sections", default="main,extras,batch,adjoint,cpu",
                     help="comma list of main, extras, batch, adjoint, cpu")
     ap.add_argument("--batch-steps", type=int, default=5000)
@@ -360,9 +360,9 @@ def main():
         extras["fp32_single_step_mlups"] = round(m1, 1)
         extras["fp32_single_step_hbm_frac"] = round(112 * n * n / (l1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         log("extra: 2048^2 fp32 control (state larger than the 256 MB last-level cache)")
-        _, m2k, l2k, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=(3, 16))
-        extras["fp32_2048_three_step_R16_mlups"] = round(m2k, 1)
-        extras["fp32_2048_hbm_frac"] = round(112 / 3 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        _, m2k, l2k, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=(4, 16))
+        extras["fp32_2048_four_step_R16_mlups"] = round(m2k, 1)
+        extras["fp32_2048_hbm_frac"] = round(112 / 4 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         out["extras"] = extras
     if "batch" in sections:
         log("batch: 64-cavity Ra x Pr sweep vs one by one")
