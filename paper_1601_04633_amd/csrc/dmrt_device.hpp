@@ -66,7 +66,7 @@ __device__ __forceinline__ double wave_sum(double v)
 // the horizontal force is zero (the cavity, G = (0, G_y) of Eq. 27) and its
 // terms are left out.
 template <typename real, bool GX = false>
-__device__ __forceinline__ void collide(real (&f)[9], real (&g)[5], const Coef<real>& c,
+__host__ __device__ __forceinline__ void collide(real (&f)[9], real (&g)[5], const Coef<real>& c,
                                         real& theta_out, real& ux_out, real& uy_out)
 {
     const real two = real(2), four = real(4);
@@ -340,85 +340,99 @@ __global__ void __launch_bounds__(1024) step_nu_kernel(StepArgs<real> A, const d
 // ---------------------------------------------------------------------------
 // Adjoint (reverse mode) of the step
 // ---------------------------------------------------------------------------
-// Vector-Jacobian product of collide() at the pre-collision state (f, g):
-// on entry lf, lg hold the adjoints of the post-collision populations, on
-// exit the adjoints of the pre-collision ones.  Derived by hand from the
-// moment form of collide(): the M^T reconstruction transposes into M
-// applied to lf (and N to lg); the relaxation, the equilibria of Eq. 34 and
-// Eq. 42 and the force image of Eq. 26 contribute through drho, u, v and
-// theta (G_y = gbeta theta + gy0).
+// Vector-Jacobian product of collide() at the pre-collision state (f, g)
+// for the cavity (G_x = 0): on entry lf, lg hold the adjoints of the
+// post-collision populations, on exit the adjoints of the pre-collision
+// ones.  Derived by hand from the moment form of collide(): since
+// f* = f + M^T a, the adjoints of the scaled moment changes are La = M lf
+// (the forward moment transform applied to lf); they flow back through the
+// relaxation, the equilibria of Eq. 34 and Eq. 42 and the force image of
+// Eq. 26 into drho, u, v, theta and the non-conserved moments, and return
+// to the populations as lf += M^T (Ldrho, Lu, Lv, Lm3, ..., Lm8) (the
+// forward reconstruction, here with density and momentum terms), likewise
+// lg += N^T (...) + Ltheta for D2Q5.
 template <typename real>
-__device__ __forceinline__ void collide_vjp(const real (&f)[9], const real (&g)[5], const Coef<real>& c,
+__host__ __device__ __forceinline__ void collide_vjp(const real (&f)[9], const real (&g)[5], const Coef<real>& c,
                                             real (&lf)[9], real (&lg)[5])
 {
-    const real two = real(2), three = real(3), six = real(6);
-    const real u = (f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6]);
-    const real v = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
-    const real theta = g[0] + (g[1] + g[3]) + (g[2] + g[4]);
-    const real uu = u * u, vv = v * v, q2 = uu + vv;
-    const real Gx = c.gx;
-    const real Gy = c.gbeta * theta + c.gy0;
-    const real Gu = Gx * u + Gy * v;
-    const real sn = c.s_nu, sq = c.s_q;
+    const real two = real(2), four = real(4);
+    // forward quantities at the pre-collision state, as in collide()
+    const real d13 = f[1] - f[3], d24 = f[2] - f[4], d57 = f[5] - f[7], d86 = f[8] - f[6];
+    const real u = d13 + (d57 + d86), v = d24 + (d57 - d86);
+    const real theta = g[0] + ((g[1] + g[3]) + (g[2] + g[4]));
+    const real uu = u * u, vv = v * v, uv = u * v;
+    const real q2 = uu + vv, e4 = uu - vv;
+    const real Gy = fmr(c.gbeta, theta, c.gy0);
+    const real Gv = Gy * v, Gu = Gy * u;
+    const real h3 = fmr(real(-0.25), q2, real(1.0 / 6.0));
 
-    // adjoints of the moment changes: (M lf)_k / |row k|^2
-    const real l1234 = (lf[1] + lf[3]) + (lf[2] + lf[4]);
-    const real l5678 = (lf[5] + lf[7]) + (lf[6] + lf[8]);
-    const real L2 = ((lf[2] - lf[4]) + (lf[5] - lf[7]) + (lf[6] - lf[8])) * real(1.0 / 6.0);
-    const real L3 = (two * l5678 - l1234 - real(4) * lf[0]) * real(1.0 / 36.0);
-    const real L4 = ((lf[1] + lf[3]) - (lf[2] + lf[4])) * real(0.25);
-    const real L5 = ((lf[5] + lf[7]) - (lf[6] + lf[8])) * real(0.25);
-    const real L6 = (two * (lf[3] - lf[1]) + (lf[5] - lf[7]) + (lf[8] - lf[6])) * real(1.0 / 12.0);
-    const real L7 = (two * (lf[4] - lf[2]) + (lf[5] - lf[7]) + (lf[6] - lf[8])) * real(1.0 / 12.0);
-    const real L8 = (real(4) * lf[0] - two * l1234 + l5678) * real(1.0 / 36.0);
+    // La = M lf
+    const real lp13 = lf[1] + lf[3], lp24 = lf[2] + lf[4], lp57 = lf[5] + lf[7], lp68 = lf[6] + lf[8];
+    const real ld13 = lf[1] - lf[3], ld24 = lf[2] - lf[4], ld57 = lf[5] - lf[7], ld86 = lf[8] - lf[6];
+    const real ls1234 = lp13 + lp24, ls5678 = lp57 + lp68;
+    const real lw = ld57 + ld86, lz = ld57 - ld86;
+    const real La2 = ld24 + lz;
+    const real La3 = fmr(-four, lf[0], fmr(two, ls5678, -ls1234));
+    const real La4 = lp13 - lp24;
+    const real La5 = lp57 - lp68;
+    const real La6 = fmr(-two, ld13, lw);
+    const real La7 = fmr(-two, ld24, lz);
+    const real La8 = fmr(four, lf[0], fmr(-two, ls1234, ls5678));
 
-    // through the non-conserved moments (relaxation)
-    const real mu3 = -sn * L3, mu4 = -sn * L4, mu5 = -sn * L5;
-    const real mu6 = -sq * L6, mu7 = -sq * L7, mu8 = -sn * L8;
-    // through drho (energy equilibria)
-    const real ldrho = sn * (L8 - two * L3);
-    // through u and v (equilibria and force image)
-    const real L38 = L3 - L8;
-    const real dF3du = three * Gx * (two - three * q2) - real(18) * u * Gu;
-    const real dF3dv = three * Gy * (two - three * q2) - real(18) * v * Gu;
-    const real dF4du = Gx * (two - real(9) * uu + three * vv) - six * Gy * u * v;
-    const real dF4dv = six * Gx * u * v - Gy * (two + three * uu - real(9) * vv);
-    const real dF5du = Gy * (real(1) - three * vv) - six * Gx * u * v;
-    const real dF5dv = Gx * (real(1) - three * uu) - six * Gy * u * v;
-    real lu = L38 * (dF3du + six * sn * u) + L4 * (dF4du + two * sn * u) + L5 * (dF5du + sn * v) +
-              L6 * (six * Gy * v - sq) + L7 * (six * (Gx * v + Gy * u));
-    real lv = L38 * (dF3dv + six * sn * v) + L4 * (dF4dv - two * sn * v) + L5 * (dF5dv + sn * u) +
-              L6 * (six * (Gy * u + Gx * v)) + L7 * (six * Gx * u - sq);
-    // through G_y (buoyancy of Eq. 27)
-    const real lGy = L2 + L38 * three * v * (two - three * q2) - L4 * v * (two + three * uu - three * vv) +
-                     L5 * u * (real(1) - three * vv) + L6 * six * u * v - L7 * (real(1) - three * uu);
+    // relaxation: a_k = -s_k/|row k|^2 r_k + F_k, r_k = m_k - m_k^eq
+    const real Lr3 = c.nsn36 * La3, Lr8 = c.nsn36 * La8;
+    const real Lr4 = c.nsn4 * La4, Lr5 = c.nsn4 * La5;
+    const real Lr6 = c.nsq12 * La6, Lr7 = c.nsq12 * La7;
+    // force image (F3 = Gv h3 enters a3 and -a8; F4 = Gv (-1/2 - 3/4 e4);
+    // F5 = Gu (1/4 - 3/4 v^2); F6 = Gy uv/2; F7 = Gy (u^2/4 - 1/12))
+    const real LF3 = La3 - La8;
+    const real LGv = fmr(LF3, h3, La4 * fmr(real(-0.75), e4, real(-0.5)));
+    const real LGu = La5 * fmr(real(-0.75), vv, real(0.25));
+    // the quadratic terms of the equilibria and of the force image
+    const real Lq2 = fmr(real(-0.25) * Gv, LF3, real(3) * (Lr8 - Lr3));
+    const real E = fmr(real(-0.75) * Gv, La4, -Lr4);                   // d/d(u^2 - v^2)
+    const real Luu = fmr(real(0.25) * Gy, La7, Lq2 + E);
+    const real Lvv = fmr(real(-0.75) * Gu, La5, Lq2 - E);
+    const real Luv = fmr(real(0.5) * Gy, La6, -Lr5);
+    const real LGy = fmr(LGu, u, fmr(LGv, v, fmr(La7, fmr(real(0.25), uu, real(-1.0 / 12.0)),
+                                                 fmr(La6, real(0.5) * uv, La2 * real(1.0 / 6.0)))));
 
-    // D2Q5: adjoints of the moment changes (N lg)_k / |row k|^2
-    const real K1 = (lg[1] - lg[3]) * real(0.5);
-    const real K2 = (lg[2] - lg[4]) * real(0.5);
-    const real K3 = ((lg[1] + lg[3]) + (lg[2] + lg[4]) - real(4) * lg[0]) * real(0.05);
-    const real K4 = ((lg[1] + lg[3]) - (lg[2] + lg[4])) * real(0.25);
-    const real ln1 = -c.sk * K1, ln2 = -c.sk * K2, ln3 = -c.se * K3, ln4 = -c.sn * K4;
-    lu += c.sk * theta * K1;
-    lv += c.sk * theta * K2;
-    const real lth = c.sk * (u * K1 + v * K2) + c.se * c.a * K3 + c.gbeta * lGy;
+    // D2Q5: b1 = -sk/2 (n1 - u theta), b2 = -sk/2 (n2 - v theta),
+    // b3 = -se/20 (n3 - a theta), b4 = -snu/4 n4
+    const real lg13 = lg[1] + lg[3], lg24 = lg[2] + lg[4];
+    const real Ln1 = c.nsk2 * (lg[1] - lg[3]);
+    const real Ln2 = c.nsk2 * (lg[2] - lg[4]);
+    const real Ln3 = c.nse20 * fmr(-four, lg[0], lg13 + lg24);
+    const real Ln4 = c.nsg4 * (lg13 - lg24);
 
-    // pre-collision adjoints: identity + M^T (moment adjoints) + N^T (...)
-    const real d2 = two * mu3 + mu8;
-    lf[0] += ldrho + real(4) * (mu8 - mu3);
-    lf[1] += ldrho + lu - mu3 + mu4 - two * mu6 - two * mu8;
-    lf[2] += ldrho + lv - mu3 - mu4 - two * mu7 - two * mu8;
-    lf[3] += ldrho - lu - mu3 + mu4 + two * mu6 - two * mu8;
-    lf[4] += ldrho - lv - mu3 - mu4 + two * mu7 - two * mu8;
-    lf[5] += ldrho + d2 + (lu + lv) + (mu5 + mu6 + mu7);
-    lf[6] += ldrho + d2 + (lv - lu) + (mu7 - mu5 - mu6);
-    lf[7] += ldrho + d2 - (lu + lv) + (mu5 - mu6 - mu7);
-    lf[8] += ldrho + d2 + (lu - lv) + (mu6 - mu5 - mu7);
-    lg[0] += lth - real(4) * ln3;
-    lg[1] += lth + ln1 + ln3 + ln4;
-    lg[2] += lth + ln2 + ln3 - ln4;
-    lg[3] += lth - ln1 + ln3 + ln4;
-    lg[4] += lth - ln2 + ln3 - ln4;
+    const real Lu = fmr(-theta, Ln1, fmr(two * u, Luu, fmr(v, Luv, fmr(LGu, Gy, Lr6))));
+    const real Lv = fmr(-theta, Ln2, fmr(two * v, Lvv, fmr(u, Luv, fmr(LGv, Gy, Lr7))));
+    const real Ldrho = fmr(two, Lr3, -Lr8);
+    const real Lth = fmr(-c.a, Ln3, fmr(-v, Ln2, fmr(-u, Ln1, c.gbeta * LGy)));
+
+    // lf += M^T (Ldrho, Lu, Lv, Lr3, Lr4, Lr5, Lr6, Lr7, Lr8)
+    const real A = fmr(-two, Lr8, -Lr3) + Ldrho;
+    const real D = fmr(two, Lr3, Lr8) + Ldrho;
+    const real P = A + Lr4, Q = A - Lr4;
+    const real U1 = fmr(-two, Lr6, Lu), V1 = fmr(-two, Lr7, Lv);
+    const real X = Lu + Lr6, Y = Lv + Lr7;
+    const real S = X + Y, T = Y - X, Rp = D + Lr5, Rm = D - Lr5;
+    lf[0] = fmr(four, Lr8 - Lr3, lf[0] + Ldrho);
+    lf[1] += P + U1;
+    lf[3] += P - U1;
+    lf[2] += Q + V1;
+    lf[4] += Q - V1;
+    lf[5] += Rp + S;
+    lf[7] += Rp - S;
+    lf[6] += Rm + T;
+    lf[8] += Rm - T;
+    // lg += N^T (., Ln1, Ln2, Ln3, Ln4) + Ltheta
+    const real t34 = (Ln3 + Ln4) + Lth, t34m = (Ln3 - Ln4) + Lth;
+    lg[0] = fmr(-four, Ln3, lg[0] + Lth);
+    lg[1] += Ln1 + t34;
+    lg[3] += t34 - Ln1;
+    lg[2] += Ln2 + t34m;
+    lg[4] += t34m - Ln2;
 }
 
 template <typename real>
