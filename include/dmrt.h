@@ -72,6 +72,16 @@ extern "C" {
 #define DMRT_Q5_FIXED_A 0   /* a given; sigma_k from Eq. 43; sigma_e = sigma_nu from Eq. 39 */
 #define DMRT_Q5_PAPER   1   /* Eq. 40 literally; a = 20 sqrt(3) alpha - 4, must be < 1     */
 
+/* Collision operator.  MRT is the paper's scheme (Eqs. 28 and 36).  LBGK is
+ * the double single-relaxation-time scheme the paper's introduction
+ * contrasts it with: every non-conserved moment of f relaxes at s_nu
+ * (s_q = s_nu) and every non-conserved moment of g at sigma_k
+ * (sigma_e = sigma_nu = sigma_k), which is the BGK collision
+ * f* = f - s_nu (f - f^eq) + F, g* = g - sigma_k (g - g^eq) written in
+ * moment space; same kernels, same cost. */
+#define DMRT_COLL_MRT  0
+#define DMRT_COLL_LBGK 1
+
 /* Wall configuration.  CAVITY is the paper's problem; the others are test
  * boxes that share the same kernel: PERIODIC (no walls), CHANNEL_X
  * (periodic in x, no-slip adiabatic walls at y = 0 and y = n) and
@@ -95,6 +105,7 @@ typedef struct {
     double force_x;         /* constant horizontal body force (test modes only;    *
                              * DMRT_BC_CAVITY requires 0, else EINVAL), 0          */
     double theta_ref;       /* reference temperature of Eq. 27 (default 0)         */
+    int    collision;       /* DMRT_COLL_MRT (default) or DMRT_COLL_LBGK           */
 } dmrt_params;
 
 /* Derived lattice parameters (Eqs. 9, 11-13, 32, 38-43). */
@@ -111,7 +122,7 @@ typedef struct dmrt_cavity dmrt_cavity;   /* opaque, library-owned */
 
 /* Fill *p with the defaults: n = 64, Ra = 1e3, Pr = 0.01, Ma = 0.1, walls
  * +-0.5, FP64, FIXED_A with a = -2/3, CAVITY, gbeta derived, no force_x,
- * theta_ref = 0.  Returns DMRT_EINVAL if p is NULL. */
+ * theta_ref = 0, MRT collision.  Returns DMRT_EINVAL if p is NULL. */
 int dmrt_params_default(dmrt_params *p);
 
 /* Parameter map of Eq. 9 / Eqs. 11-13 (H = n, c_s^2 = 1/3):

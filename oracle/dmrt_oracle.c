@@ -36,6 +36,14 @@
  *       equals the printed 2 sqrt(3) alpha theta_w when Eq. 40 holds.
  *   R7  Eq. 18: the wall gradient is the second-order one-sided difference
  *       through the wall value and the first two node centres.
+ *
+ * Besides the double MRT scheme the oracle runs the double LBGK scheme the
+ * paper's introduction contrasts it with (one relaxation time for f and
+ * one for g, He et al.'s double-distribution approach): the collision is
+ * then done in distribution space, f* = f - (f - f^eq)/tau_f + F and
+ * g* = g - (g - g^eq)/tau_g, with the textbook second-order equilibria and
+ * 1/tau_f = s_nu (Eq. 32's viscosity relation), 1/tau_g = sigma_k (Eq. 43's
+ * diffusivity relation).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -43,11 +51,13 @@
 
 enum { ORC_CAVITY = 0, ORC_PERIODIC = 1, ORC_CHANNEL_X = 2, ORC_ADIABATIC_BOX = 3 };
 enum { ORC_Q5_FIXED_A = 0, ORC_Q5_PAPER = 1 };
+enum { ORC_MRT = 0, ORC_LBGK = 1 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EUNSTABLE = -2, ORC_ENOMEM = -3 };
 
 typedef struct {
     int n;                       /* nodes per side; walls half a link outside */
     int bc;
+    int collision;               /* ORC_MRT or ORC_LBGK */
     double rho0;
     /* physical parameters in lattice units */
     double H, nu, alpha, gbeta, force_x, theta_ref;
@@ -73,9 +83,10 @@ typedef struct {
 /* ---------------------------------------------------------------------- */
 int orc_derive(int n, double Ra, double Pr, double Ma, double theta_hot,
                double theta_cold, int q5_mode, double a_fixed,
-               double gbeta_override, double *out)
+               double gbeta_override, int collision, double *out)
 {
     if (n < 2 || !out) return ORC_EINVAL;
+    if (collision != ORC_MRT && collision != ORC_LBGK) return ORC_EINVAL;
     if (!isfinite(Ra) || !isfinite(Pr) || !isfinite(Ma) || !isfinite(theta_hot) ||
         !isfinite(theta_cold))
         return ORC_EINVAL;
@@ -112,6 +123,12 @@ int orc_derive(int n, double Ra, double Pr, double Ma, double theta_hot,
         se = sn = 1.0 / (0.5 + 1.0 / (6.0 * lam_k));
     } else {
         return ORC_EINVAL;
+    }
+    if (collision == ORC_LBGK) {
+        /* one relaxation time per distribution: every non-conserved moment
+         * relaxes at the viscous rate (f) or at the diffusive rate (g) */
+        s_q = s_nu;
+        se = sn = sk;
     }
     if (!(a > -4.0 && a < 1.0)) return ORC_EUNSTABLE;   /* stability: a < 1 */
     double rel[5] = { s_nu, s_q, sk, se, sn };
@@ -211,17 +228,17 @@ void orc_destroy(orc_t *s)
 orc_t *orc_create(int n, double Ra, double Pr, double Ma, double theta_hot,
                   double theta_cold, int q5_mode, double a_fixed, int bc,
                   double gbeta_override, double force_x, double theta_ref,
-                  int *err)
+                  int collision, int *err)
 {
     double d[12];
     int rc = orc_derive(n, Ra, Pr, Ma, theta_hot, theta_cold, q5_mode, a_fixed,
-                        gbeta_override, d);
+                        gbeta_override, collision, d);
     if (rc == ORC_OK && (bc < 0 || bc > 3 || !isfinite(force_x) || !isfinite(theta_ref)))
         rc = ORC_EINVAL;
     if (rc != ORC_OK) { if (err) *err = rc; return NULL; }
     orc_t *s = (orc_t *)calloc(1, sizeof(orc_t));
     if (!s) { if (err) *err = ORC_ENOMEM; return NULL; }
-    s->n = n; s->bc = bc; s->rho0 = 1.0;
+    s->n = n; s->bc = bc; s->rho0 = 1.0; s->collision = collision;
     s->nu = d[0]; s->alpha = d[1]; s->gbeta = d[2]; s->a = d[8]; s->H = d[11];
     s->force_x = force_x; s->theta_ref = theta_ref;
     s->theta_hot = theta_hot; s->theta_cold = theta_cold;
@@ -337,9 +354,53 @@ int orc_force(const orc_t *s, double Gx, double Gy, double u, double v, double *
 }
 
 /* One node: pre-collision f[9], g[5] -> post-collision fs[9], gs[5]. */
+/* Double LBGK collision in distribution space.  The D2Q9 equilibrium is the
+ * second-order polynomial w_i [drho + rho0 (3 e.u + 9/2 (e.u)^2 - 3/2 u^2)]
+ * (f stored as the deviation from w_i rho0, as in Eq. 33); the D2Q5 one is
+ * w_i theta + theta (c_i.u)/2, whose moments are those of Eq. 42. */
+static void collide_lbgk(const orc_t *s, const double *f, const double *g, double *fs, double *gs)
+{
+    static const double w9[9] = { 4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36 };
+    double drho = 0.0, jx = 0.0, jy = 0.0, theta = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        drho += f[i];
+        jx += s->e[i][0] * f[i];
+        jy += s->e[i][1] * f[i];
+    }
+    for (int i = 0; i < 5; ++i) theta += g[i];
+    double u = jx / s->rho0, v = jy / s->rho0, uu = u * u + v * v;
+    double omega_f = s->S[4], omega_g = s->Q[1];
+    double F[9];
+    orc_force(s, s->force_x, s->gbeta * (theta - s->theta_ref), u, v, F);
+    for (int i = 0; i < 9; ++i) {
+        double eu = s->e[i][0] * u + s->e[i][1] * v;
+        double feq = w9[i] * (drho + s->rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+        fs[i] = f[i] - omega_f * (f[i] - feq) + F[i];
+    }
+    double w0 = (1.0 - s->a) / 5.0, wm = (4.0 + s->a) / 20.0;
+    for (int i = 0; i < 5; ++i) {
+        double cu = s->c5[i][0] * u + s->c5[i][1] * v;
+        double geq = (i == 0 ? w0 : wm) * theta + 0.5 * theta * cu;
+        gs[i] = g[i] - omega_g * (g[i] - geq);
+    }
+}
+
+/* Test hook: replace the relaxation rates of Eqs. 31 and 38. */
+int orc_set_rates(orc_t *s, const double *S9, const double *Q5)
+{
+    memcpy(s->S, S9, sizeof s->S);
+    memcpy(s->Q, Q5, sizeof s->Q);
+    return ORC_OK;
+}
+
 int orc_collide(const orc_t *s, const double *f, const double *g, double *fs, double *gs)
 {
     double m[9], meq[9], mst[9], n5[5], neq[5], nst[5], F[9];
+    if (s->collision == ORC_LBGK) {
+        collide_lbgk(s, f, g, fs, gs);
+        return ORC_OK;
+    }
     /* Eq. 33 and Eq. 41 */
     matvec(9, &s->M[0][0], f, m);
     double drho = m[0];

@@ -27,6 +27,7 @@ SRC_PATH = os.path.join(_HERE, "dmrt_oracle.c")
 
 CAVITY, PERIODIC, CHANNEL_X, ADIABATIC_BOX = 0, 1, 2, 3
 Q5_FIXED_A, Q5_PAPER = 0, 1
+MRT, LBGK = 0, 1
 OK, EINVAL, EUNSTABLE, ENOMEM = 0, -1, -2, -3
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -56,12 +57,14 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         L.orc_derive.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                 ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp]
+                                 ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 _dp]
         L.orc_derive.restype = ctypes.c_int
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, _ip]
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int, _ip]
         L.orc_create.restype = ctypes.c_void_p
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_destroy.restype = None
@@ -71,6 +74,7 @@ def lib():
             ("orc_force", [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                            ctypes.c_double, ctypes.c_double, _dp]),
             ("orc_collide", [ctypes.c_void_p, _dp, _dp, _dp, _dp]),
+            ("orc_set_rates", [ctypes.c_void_p, _dp, _dp]),
             ("orc_set_equilibrium", [ctypes.c_void_p, _dp, _dp, _dp, _dp]),
             ("orc_set_hot_wall", [ctypes.c_void_p, _dp]),
             ("orc_get_state", [ctypes.c_void_p, _dp, _dp]),
@@ -113,10 +117,10 @@ DERIVED_KEYS = ("nu", "alpha", "gbeta", "s_nu", "s_q", "sigma_k", "sigma_e",
 
 
 def derive(n, Ra, Pr, Ma, theta_hot=0.5, theta_cold=-0.5, q5_mode=Q5_FIXED_A,
-           a=-2.0 / 3.0, gbeta_override=math.nan):
+           a=-2.0 / 3.0, gbeta_override=math.nan, collision=MRT):
     out = np.zeros(12)
     _check(lib().orc_derive(n, Ra, Pr, Ma, theta_hot, theta_cold, q5_mode, a,
-                            gbeta_override, _ptr(out)))
+                            gbeta_override, collision, _ptr(out)))
     return dict(zip(DERIVED_KEYS, out.tolist()))
 
 
@@ -125,10 +129,10 @@ class Oracle:
 
     def __init__(self, n, Ra, Pr, Ma=0.1, theta_hot=0.5, theta_cold=-0.5,
                  q5_mode=Q5_FIXED_A, a=-2.0 / 3.0, bc=CAVITY,
-                 gbeta_override=math.nan, force_x=0.0, theta_ref=0.0):
+                 gbeta_override=math.nan, force_x=0.0, theta_ref=0.0, collision=MRT):
         err = ctypes.c_int(0)
         h = lib().orc_create(n, Ra, Pr, Ma, theta_hot, theta_cold, q5_mode, a, bc,
-                             gbeta_override, force_x, theta_ref, ctypes.byref(err))
+                             gbeta_override, force_x, theta_ref, collision, ctypes.byref(err))
         if not h:
             raise OracleError(err.value)
         self._h = h
@@ -163,6 +167,12 @@ class Oracle:
         fs = np.zeros(9); gs = np.zeros(5)
         _check(lib().orc_collide(self._h, _ptr(f), _ptr(g), _ptr(fs), _ptr(gs)))
         return fs, gs
+
+    def set_rates(self, S, Q):
+        """Test hook: overwrite the relaxation rates of Eqs. 31 and 38."""
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(9)
+        Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(5)
+        _check(lib().orc_set_rates(self._h, _ptr(S), _ptr(Q)))
 
     def force(self, Gx, Gy, u, v):
         F = np.zeros(9)

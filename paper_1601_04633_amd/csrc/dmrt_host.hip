@@ -55,6 +55,7 @@ int derive(const dmrt_params* p, dmrt_derived* d)
     if (14.0 * esz * (double)((p->n + 63) / 64 * 64) * p->n >= 4294967296.0) return DMRT_EINVAL;
     if (p->bc_mode < DMRT_BC_CAVITY || p->bc_mode > DMRT_BC_ADIABATIC_BOX) return DMRT_EINVAL;
     if (p->bc_mode == DMRT_BC_CAVITY && p->force_x != 0.0) return DMRT_EINVAL;   // G = (0, G_y)
+    if (p->collision != DMRT_COLL_MRT && p->collision != DMRT_COLL_LBGK) return DMRT_EINVAL;
     if (!(p->Ra > 0.0) || !(p->Pr > 0.0) || !(p->Ma > 0.0)) return DMRT_EUNSTABLE;
     const double H = p->n;
     const double dT = p->theta_hot - p->theta_cold;
@@ -70,7 +71,7 @@ int derive(const dmrt_params* p, dmrt_derived* d)
     const double nu = p->Ma * H * std::sqrt(p->Pr / (3.0 * p->Ra));
     const double alpha = nu / p->Pr;
     const double s_nu = 2.0 / (6.0 * nu + 1.0);
-    const double s_q = 8.0 * (2.0 - s_nu) / (8.0 - s_nu);
+    double s_q = 8.0 * (2.0 - s_nu) / (8.0 - s_nu);
     double a, sk, se;
     if (p->q5_mode == DMRT_Q5_PAPER) {
         const double lk = std::sqrt(3.0) / 6.0;       // Eq. 40
@@ -86,6 +87,11 @@ int derive(const dmrt_params* p, dmrt_derived* d)
         se = 1.0 / (0.5 + 1.0 / (6.0 * lk));           // Eq. 39
     } else {
         return DMRT_EINVAL;
+    }
+    if (p->collision == DMRT_COLL_LBGK) {
+        // one rate per distribution: BGK written in moment space
+        s_q = s_nu;
+        se = sk;
     }
     if (!(a > -4.0 && a < 1.0)) return DMRT_EUNSTABLE;
     const double rates[] = {s_nu, s_q, sk, se};
@@ -339,6 +345,7 @@ int dmrt_params_default(dmrt_params* p)
     p->gbeta_override = NAN;
     p->force_x = 0.0;
     p->theta_ref = 0.0;
+    p->collision = DMRT_COLL_MRT;
     return DMRT_OK;
 }
 

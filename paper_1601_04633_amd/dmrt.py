@@ -60,7 +60,8 @@ class dmrt_params(ctypes.Structure):
                 ("theta_hot", ctypes.c_double), ("theta_cold", ctypes.c_double),
                 ("precision", ctypes.c_int), ("q5_mode", ctypes.c_int), ("a", ctypes.c_double),
                 ("bc_mode", ctypes.c_int), ("gbeta_override", ctypes.c_double),
-                ("force_x", ctypes.c_double), ("theta_ref", ctypes.c_double)]
+                ("force_x", ctypes.c_double), ("theta_ref", ctypes.c_double),
+                ("collision", ctypes.c_int)]
 
 
 class dmrt_derived(ctypes.Structure):
@@ -159,7 +160,8 @@ def exported_symbols():
 
 def make_params(n=64, Ra=1e3, Pr=0.01, Ma=0.1, theta_hot=0.5, theta_cold=-0.5,
                 precision="fp64", q5_mode=None, a=-2.0 / 3.0, bc_mode=None,
-                gbeta_override=math.nan, force_x=0.0, theta_ref=0.0) -> dmrt_params:
+                gbeta_override=math.nan, force_x=0.0, theta_ref=0.0,
+                collision=None) -> dmrt_params:
     p = dmrt_params()
     check(dmrt_params_default(ctypes.byref(p)), "dmrt_params_default")
     p.n, p.Ra, p.Pr, p.Ma = n, Ra, Pr, Ma
@@ -170,6 +172,9 @@ def make_params(n=64, Ra=1e3, Pr=0.01, Ma=0.1, theta_hot=0.5, theta_cold=-0.5,
     p.a = a
     p.bc_mode = DMRT_BC_CAVITY if bc_mode is None else bc_mode
     p.gbeta_override, p.force_x, p.theta_ref = gbeta_override, force_x, theta_ref
+    if isinstance(collision, str):
+        collision = {"mrt": DMRT_COLL_MRT, "lbgk": DMRT_COLL_LBGK}[collision.lower()]
+    p.collision = DMRT_COLL_MRT if collision is None else int(collision)
     return p
 
 

@@ -35,14 +35,15 @@ def test_params_default():
     assert D.dmrt_params_default(None) == D.DMRT_EINVAL
 
 
+@pytest.mark.parametrize("coll", [0, 1])
 @pytest.mark.parametrize("n,Ra,Pr,mode,Ma,a", [
     (64, 1e3, 0.01, 0, 0.1, -2 / 3), (256, 1e4, 0.005, 0, 0.1, -2 / 3),
     (1024, 1e5, 0.001, 0, 0.1, -2 / 3), (256, 1e4, 0.01, 0, 0.1, 0.25),
     (256, 1e4, 0.01, 1, 0.009, 0.0), (32, 1e4, 0.01, 0, 0.1, -3.0)])
-def test_derive_agrees_with_oracle(oracle_mod, n, Ra, Pr, mode, Ma, a):
-    p = D.make_params(n=n, Ra=Ra, Pr=Pr, Ma=Ma, q5_mode=mode, a=a)
+def test_derive_agrees_with_oracle(oracle_mod, n, Ra, Pr, mode, Ma, a, coll):
+    p = D.make_params(n=n, Ra=Ra, Pr=Pr, Ma=Ma, q5_mode=mode, a=a, collision=coll)
     lib = D.derive(p)
-    orc = oracle_mod.derive(n, Ra, Pr, Ma, q5_mode=mode, a=a)
+    orc = oracle_mod.derive(n, Ra, Pr, Ma, q5_mode=mode, a=a, collision=coll)
     for k, v in orc.items():
         assert math.isclose(lib[k], v, rel_tol=1e-14, abs_tol=1e-300), k
 
@@ -53,7 +54,7 @@ def test_derive_agrees_with_oracle(oracle_mod, n, Ra, Pr, mode, Ma, a):
     (dict(a=-4.0), "DMRT_EUNSTABLE"), (dict(precision=7), "DMRT_EINVAL"),
     (dict(bc_mode=9), "DMRT_EINVAL"), (dict(q5_mode=5), "DMRT_EINVAL"),
     (dict(theta_hot=-0.5), "DMRT_EINVAL"), (dict(force_x=float("inf")), "DMRT_EINVAL"),
-    (dict(force_x=1e-5), "DMRT_EINVAL"), (dict(n=8748, precision=0), "DMRT_EINVAL"),
+    (dict(force_x=1e-5), "DMRT_EINVAL"), (dict(collision=2), "DMRT_EINVAL"), (dict(n=8748, precision=0), "DMRT_EINVAL"),
     (dict(n=6178, precision=1), "DMRT_EINVAL"),
     (dict(q5_mode=1), "DMRT_EUNSTABLE"),
 ])

@@ -67,6 +67,10 @@ CASES = [
     dict(bc_mode=0, n=32, Ra=1e5, Pr=0.001, gbeta_override=0.3, theta_ref=0.1),
     dict(bc_mode=1, n=48, Ra=3e3, Pr=0.05, gbeta_override=0.2, force_x=0.05),
     dict(bc_mode=2, n=40, Ra=1e3, Pr=0.1, gbeta_override=0.0, force_x=0.1),
+    # double LBGK: the device's moment-space collision with equal rates
+    # against the oracle's distribution-space BGK
+    dict(bc_mode=0, n=256, Ra=5e4, Pr=0.005, collision=1),
+    dict(bc_mode=1, n=48, Ra=3e3, Pr=0.05, gbeta_override=0.2, force_x=0.05, collision=1),
 ]
 
 
