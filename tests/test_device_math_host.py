@@ -126,3 +126,31 @@ def test_collision_vjp_is_exact_for_the_linear_part(host_lib):
         host_lib.dmrt_host_collide_vjp(ctypes.byref(p), ctypes.byref(d), _p(f0.copy()), _p(g0.copy()),
                                        _p(a), _p(b))
         assert np.abs(np.concatenate([a, b]) - J[r]).max() <= 1e-8
+
+
+def test_collision_vjp_dot_product_identity(host_lib):
+    """<J v, w> = <v, J^T w> for the collision at random states, with J v
+    from forward-mode differentiation of the vectorised FP64 reference
+    (oracle/torch_ref.py, matrix form with M^-1, N^-1) and J^T w from the
+    device's hand-derived VJP: equal to round-off (1e-13)."""
+    torch = pytest.importorskip("torch")
+    from oracle.torch_ref import Reference
+    n, Ra, Pr = 64, 1e4, 0.01
+    ref = Reference(n, Ra, Pr)
+    p, d = _params(bc_mode=0, n=n, Ra=Ra, Pr=Pr)
+    rng = np.random.default_rng(17)
+    m = 64
+    f = rng.uniform(-0.05, 0.05, (9, 1, m))
+    g = rng.uniform(-0.4, 0.4, (5, 1, m))
+    vf, vg = rng.standard_normal((9, 1, m)), rng.standard_normal((5, 1, m))
+    wf, wg = rng.standard_normal((9, 1, m)), rng.standard_normal((5, 1, m))
+    _, (jf, jg) = torch.func.jvp(ref.collide, (torch.tensor(f), torch.tensor(g)),
+                                 (torch.tensor(vf), torch.tensor(vg)))
+    lhs = (jf.numpy() * wf).sum(axis=0)[0] + (jg.numpy() * wg).sum(axis=0)[0]
+    for k in range(m):
+        a, b = wf[:, 0, k].copy(), wg[:, 0, k].copy()
+        host_lib.dmrt_host_collide_vjp(ctypes.byref(p), ctypes.byref(d), _p(f[:, 0, k].copy()),
+                                       _p(g[:, 0, k].copy()), _p(a), _p(b))
+        rhs = a @ vf[:, 0, k] + b @ vg[:, 0, k]
+        scale = np.abs(wf[:, 0, k]).sum() + np.abs(wg[:, 0, k]).sum()
+        assert abs(lhs[k] - rhs) <= 1e-13 * scale, (k, lhs[k], rhs)
