@@ -56,9 +56,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_alg_per_launch, kernel):
-    """HBM bytes per launch from the committed counter summary, or None when
-    it is missing or was taken on a different kernel source."""
+def counter_summary(kernel):
+    """The committed counter summary of this kernel (HBM bytes per launch,
+    VALU busy fraction), or None when it is missing or was taken on a
+    different kernel source."""
     try:
         with open(TRAFFIC_FILES[kernel]) as fh:
             t = json.load(fh)
@@ -66,7 +67,13 @@ def measured_traffic(bytes_alg_per_launch, kernel):
         return None
     if t.get("kernel_hash") != kernel_hash() or t.get("kernel") != kernel:
         return None
-    return t.get("bytes_per_launch")
+    return t
+
+
+def measured_traffic(bytes_alg_per_launch, kernel):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    t = counter_summary(kernel)
+    return None if t is None else t.get("bytes_per_launch")
 
 
 def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601, temporal=None):
@@ -295,6 +302,7 @@ def main():
     kname = (f"stepk_kernel<{'float' if esz == 4 else 'double'}, {temporal[1]}, {spl}>" if spl >= 2
              else f"step_kernel<{'float' if esz == 4 else 'double'}, 0>")
     traffic = measured_traffic(alg_bytes, kname) if n == 1024 and prec == "fp32" else None
+    counters = counter_summary(kname) if n == 1024 and prec == "fp32" else None
     log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic per launch "
         f"({single_equiv:.1f} GB/s single-step equivalent), {ms_launch*1e3:.2f} us/launch, Nu {nu:.5f}")
 
@@ -323,7 +331,8 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "bytes_per_node_update": WORDS_PER_NODE * esz // spl,
                      "single_step_equivalent_GBs": round(single_equiv, 1),
-                     "single_step_equivalent_frac": round(single_equiv / HBM_PEAK_GBS, 4)},
+                     "single_step_equivalent_frac": round(single_equiv / HBM_PEAK_GBS, 4),
+                     "valu_busy_frac_counters": None if counters is None else counters.get("valu_busy_frac")},
         "launch": {"block": list(launch[:2]), "xcd_remap": launch[2], "graph_steps": launch[3],
                    "steps_per_launch": spl, "tile_rows": temporal[1]},
         "nu_hot_wall": nu,
