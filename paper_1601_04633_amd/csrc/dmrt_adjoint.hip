@@ -206,7 +206,7 @@ AdjArgs<real> adj_args(const dmrt_cavity* h, const AdjointState* a)
 // Tile grid of the K-step kernels (output tiles of (64 - 2(K-1)) x (R - 2(K-1))).
 inline void k_geometry(int n, int K, int R, int& tiles_x, int& tiles)
 {
-    const int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
+    const int W = kFootW - 2 * (K - 1), HO = R - 2 * (K - 1);
     tiles_x = (n + W - 1) / W;
     tiles = tiles_x * ((n + HO - 1) / HO);
 }
@@ -217,7 +217,7 @@ template <typename real>
 int launch_adjk(const dmrt_cavity* h, hipStream_t s, const AdjArgs<real>* A, const StepArgs<real>* F)
 {
     const int K = h->adj_temporal, R = h->adj_rows;
-    const dim3 block(kT2Width, R);
+    const dim3 block(kFootW, R);
     const long slot = A ? A->slot : (long)h->adj->slot_elems;
     auto padded = [](int t) { return (t + 7) / 8 * 8; };
 #define DMRT_AKR(KK, RR)                                                                               \

@@ -50,8 +50,8 @@ struct dmrt_batch {
     TileRef* tiles = nullptr;
     std::vector<int> group_tile_begin;   // tile range of each group, plus end
     int ntiles = 0;
-    TileRef* tiles2 = nullptr;           // footprints of the K-step kernel
-    std::vector<int> group_tile2_begin;
+    TileRef* foot_tiles = nullptr;           // footprints of the K-step kernel
+    std::vector<int> group_foot_begin;
     int temporal = 1, t_rows = 10;       // steps per launch and footprint rows
     int graph_flips[2] = {0, 0};
     double* nu = nullptr;
@@ -203,23 +203,23 @@ int build_tiles(dmrt_batch* b)
     HIPCHK(hipMalloc(&b->tiles, tiles.size() * sizeof(TileRef)));
     HIPCHK(hipMemcpyAsync(b->tiles, tiles.data(), tiles.size() * sizeof(TileRef),
                           hipMemcpyHostToDevice, b->stream));
-    // footprints of the two-step kernel, same groups and member order
+    // footprints of the K-step kernel, same groups and member order
     std::vector<TileRef> fp;
-    b->group_tile2_begin.clear();
+    b->group_foot_begin.clear();
     const int K = std::max(2, b->temporal), R = b->t_rows;
-    const int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
+    const int W = kFootW - 2 * (K - 1), HO = R - 2 * (K - 1);
     for (const auto& g : groups) {
-        b->group_tile2_begin.push_back((int)fp.size());
+        b->group_foot_begin.push_back((int)fp.size());
         for (int i : g) {
             const int n = b->p[i].n;
             for (int y0 = 0; y0 < n; y0 += HO)
                 for (int x0 = 0; x0 < n; x0 += W) fp.push_back({i, x0 - (K - 1), y0 - (K - 1), 0});
         }
     }
-    b->group_tile2_begin.push_back((int)fp.size());
-    if (b->tiles2) { (void)hipFree(b->tiles2); b->tiles2 = nullptr; }
-    HIPCHK(hipMalloc(&b->tiles2, fp.size() * sizeof(TileRef)));
-    HIPCHK(hipMemcpyAsync(b->tiles2, fp.data(), fp.size() * sizeof(TileRef), hipMemcpyHostToDevice,
+    b->group_foot_begin.push_back((int)fp.size());
+    if (b->foot_tiles) { (void)hipFree(b->foot_tiles); b->foot_tiles = nullptr; }
+    HIPCHK(hipMalloc(&b->foot_tiles, fp.size() * sizeof(TileRef)));
+    HIPCHK(hipMemcpyAsync(b->foot_tiles, fp.data(), fp.size() * sizeof(TileRef), hipMemcpyHostToDevice,
                           b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     return DMRT_OK;
@@ -250,11 +250,11 @@ int launch_rangek_t(dmrt_batch* b, hipStream_t s, int t0, int t1, int from)
     if (span <= 0) return DMRT_OK;
     const int grid = b->grid_blocks > 0 ? std::min(span, b->grid_blocks) : span;
     const CavityDev<real>* cv = static_cast<const CavityDev<real>*>(b->cavs);
-    const dim3 block(kT2Width, b->t_rows);
+    const dim3 block(kFootW, b->t_rows);
     const int K = b->temporal, R = b->t_rows;
 #define DMRT_BKR(KK, RR)                                                                             \
     if (K == KK && R == RR) {                                                                         \
-        hipLaunchKernelGGL((batch_stepk_kernel<real, RR, KK>), dim3(grid), block, 0, s, cv, b->tiles2, \
+        hipLaunchKernelGGL((batch_stepk_kernel<real, RR, KK>), dim3(grid), block, 0, s, cv, b->foot_tiles, \
                            t0, t1, from);                                                             \
         HIPCHK(hipGetLastError());                                                                    \
         return DMRT_OK;                                                                               \
@@ -279,8 +279,8 @@ int enqueue_round(dmrt_batch* b, hipStream_t s, int from, int steps, int* flips)
         while (k > 0) {
             int rc;
             if (b->temporal >= 2 && k >= b->temporal) {
-                rc = b->esz == 8 ? launch_rangek_t<double>(b, s, b->group_tile2_begin[g], b->group_tile2_begin[g + 1], c)
-                                 : launch_rangek_t<float>(b, s, b->group_tile2_begin[g], b->group_tile2_begin[g + 1], c);
+                rc = b->esz == 8 ? launch_rangek_t<double>(b, s, b->group_foot_begin[g], b->group_foot_begin[g + 1], c)
+                                 : launch_rangek_t<float>(b, s, b->group_foot_begin[g], b->group_foot_begin[g + 1], c);
                 k -= b->temporal;
             } else {
                 rc = launch_range(b, s, b->group_tile_begin[g], b->group_tile_begin[g + 1], c);
@@ -619,7 +619,7 @@ int dmrt_batch_destroy(dmrt_batch* b)
     if (!b) return DMRT_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graphs(b);
-    void* ptrs[] = {b->arena, b->thw_real, b->thw_d, b->cavs, b->tiles, b->tiles2, b->nu, b->flags,
+    void* ptrs[] = {b->arena, b->thw_real, b->thw_d, b->cavs, b->tiles, b->foot_tiles, b->nu, b->flags,
                     b->scratch};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);

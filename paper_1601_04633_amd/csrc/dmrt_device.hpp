@@ -626,17 +626,17 @@ static __global__ void __launch_bounds__(256) sum_kernel(const double* __restric
 // lie in the previous phase's region, so the K steps equal K single-step
 // launches exactly.  Global traffic per node update: about 28 / K words
 // instead of 28 (the footprint ring's re-reads hit L2).
-constexpr int kT2Width = 64;         // footprint width (one wavefront)
+constexpr int kFootW = 64;         // footprint width (one wavefront)
 
 template <typename real, int R>
-__device__ __forceinline__ real t2_lds(const real* lds, int q, int ly, int lx)
+__device__ __forceinline__ real lds_at(const real* lds, int q, int ly, int lx)
 {
-    return lds[(q * R + ly) * kT2Width + lx];
+    return lds[(q * R + ly) * kFootW + lx];
 }
 
-// Phase 1 of the two-step update: s(t+1) at footprint node (x, y) into LDS.
+// First phase of the K-step update: s(t+1) at footprint node (x, y) into LDS.
 template <typename real, int R>
-__device__ __forceinline__ void t2_phase1(real* lds, const real* __restrict__ fi,
+__device__ __forceinline__ void lds_first_phase(real* lds, const real* __restrict__ fi,
                                           const real* __restrict__ gi, const real* __restrict__ thw,
                                           int n, int pitch, int P, int x, int y, int lx, int ly,
                                           const Coef<real>& c)
@@ -646,9 +646,9 @@ __device__ __forceinline__ void t2_phase1(real* lds, const real* __restrict__ fi
     real th, ux, uy;
     collide<real>(f, g, c, th, ux, uy);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
+    for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = f[i];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+    for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kFootW + lx] = g[i];
 }
 
 // Gather of s(t+j-1) for node (x, y) from LDS with the cavity's wall rules.
@@ -657,11 +657,11 @@ __device__ __forceinline__ void t2_phase1(real* lds, const real* __restrict__ fi
 // a wall then replace the links that cross it by the bounce-back values of
 // their own node.
 template <typename real, int R>
-__device__ __forceinline__ void t2_gather_lds(const real* lds, const real* __restrict__ thw, int n,
+__device__ __forceinline__ void gather_lds(const real* lds, const real* __restrict__ thw, int n,
                                               int x, int y, int lx, int ly, const Coef<real>& c,
                                               real (&f)[9], real (&g)[5])
 {
-    constexpr int W = kT2Width, PL = R * kT2Width;
+    constexpr int W = kFootW, PL = R * kFootW;
     const real* b = lds + (ly * W + lx);
     f[0] = b[0];
     f[1] = b[1 * PL - 1];
@@ -692,12 +692,12 @@ __device__ __forceinline__ void t2_gather_lds(const real* lds, const real* __res
 
 // Last phase: the final step at output node (x, y) from LDS, stored to global.
 template <typename real, int R>
-__device__ __forceinline__ void t2_phase2(const real* lds, real* __restrict__ fo, real* __restrict__ go,
+__device__ __forceinline__ void lds_last_phase(const real* lds, real* __restrict__ fo, real* __restrict__ go,
                                           const real* __restrict__ thw, int n, int pitch, int P, int x,
                                           int y, int lx, int ly, const Coef<real>& c)
 {
     real f[9], g[5];
-    t2_gather_lds<real, R>(lds, thw, n, x, y, lx, ly, c, f, g);
+    gather_lds<real, R>(lds, thw, n, x, y, lx, ly, c, f, g);
     real th, ux, uy;
     collide<real>(f, g, c, th, ux, uy);
     const unsigned kb = unsigned(y * pitch + x) * sizeof(real), Pb = unsigned(P) * sizeof(real);
@@ -718,7 +718,7 @@ __device__ __forceinline__ void t2_phase2(const real* lds, real* __restrict__ fo
 template <typename real, int R, int K, bool ALL>
 __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, int tile, long slot)
 {
-    constexpr int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
+    constexpr int W = kFootW - 2 * (K - 1), HO = R - 2 * (K - 1);
     static_assert(W > 0 && HO > 0, "tile too small for K steps");
     const int tyt = tile / A.tiles_x;
     const int txt = tile - tyt * A.tiles_x;
@@ -727,7 +727,7 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
     const int y = tyt * HO - (K - 1) + ly;
     const int n = A.n, P = A.plane, k = y * A.pitch + x;
     const bool inside = x >= 0 && x < n && y >= 0 && y < n;
-    const bool own = inside && lx >= K - 1 && lx <= kT2Width - K && ly >= K - 1 && ly <= R - K;
+    const bool own = inside && lx >= K - 1 && lx <= kFootW - K && ly >= K - 1 && ly <= R - K;
     real f[9], g[5];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = real(0);
@@ -738,9 +738,9 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
         real th, ux, uy;
         collide<real>(f, g, A.c, th, ux, uy);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
+        for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = f[i];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+        for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kFootW + lx] = g[i];
         if (ALL && own) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) A.fout[i * P + k] = f[i];
@@ -751,18 +751,18 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
     __syncthreads();
 #pragma unroll
     for (int j = 2; j < K; ++j) {
-        const bool act = inside && lx >= j - 1 && lx <= kT2Width - j && ly >= j - 1 && ly <= R - j;
+        const bool act = inside && lx >= j - 1 && lx <= kFootW - j && ly >= j - 1 && ly <= R - j;
         if (act) {
-            t2_gather_lds<real, R>(lds, A.thw, n, x, y, lx, ly, A.c, f, g);
+            gather_lds<real, R>(lds, A.thw, n, x, y, lx, ly, A.c, f, g);
             real th, ux, uy;
             collide<real>(f, g, A.c, th, ux, uy);
         }
         __syncthreads();
         if (act) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
+            for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = f[i];
 #pragma unroll
-            for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+            for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kFootW + lx] = g[i];
             if (ALL && own) {
                 real* fo = A.fout + (j - 1) * slot;
                 real* go = A.gout + (j - 1) * slot;
@@ -776,13 +776,13 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
     }
     if (!own) return;
     const long last = ALL ? (K - 1) * slot : 0;
-    t2_phase2<real, R>(lds, A.fout + last, A.gout + last, A.thw, n, A.pitch, P, x, y, lx, ly, A.c);
+    lds_last_phase<real, R>(lds, A.fout + last, A.gout + last, A.thw, n, A.pitch, P, x, y, lx, ly, A.c);
 }
 
 template <typename real, int R, int K>
-__global__ void __launch_bounds__(kT2Width * R) stepk_kernel(StepArgs<real> A)
+__global__ void __launch_bounds__(kFootW * R) stepk_kernel(StepArgs<real> A)
 {
-    __shared__ real lds[14 * R * kT2Width];
+    __shared__ real lds[14 * R * kFootW];
     const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
     if (tile >= A.tiles) return;                      // uniform per workgroup
     stepk_tile<real, R, K, false>(A, lds, tile, 0);
@@ -790,9 +790,9 @@ __global__ void __launch_bounds__(kT2Width * R) stepk_kernel(StepArgs<real> A)
 
 // K forward steps storing every state (the adjoint's recompute on its own).
 template <typename real, int R, int K>
-__global__ void __launch_bounds__(kT2Width * R) stepk_all_kernel(StepArgs<real> A, long slot)
+__global__ void __launch_bounds__(kFootW * R) stepk_all_kernel(StepArgs<real> A, long slot)
 {
-    __shared__ real lds[14 * R * kT2Width];
+    __shared__ real lds[14 * R * kFootW];
     const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
     if (tile >= A.tiles) return;
     stepk_tile<real, R, K, true>(A, lds, tile, slot);
@@ -805,7 +805,7 @@ template <typename real, int R>
 __device__ __forceinline__ void adj_pull_lds(const real* lds, int n, int x, int y, int lx, int ly,
                                              real sd, real (&lf)[9], real (&lg)[5])
 {
-    constexpr int W = kT2Width, PL = R * kT2Width;
+    constexpr int W = kFootW, PL = R * kFootW;
     const real* b = lds + (ly * W + lx);
     lf[0] = b[0];
     lf[1] = b[1 * PL + 1];
@@ -844,7 +844,7 @@ __device__ __forceinline__ void adj_pull_lds(const real* lds, int n, int x, int 
 template <typename real, int R, int K>
 __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int tile)
 {
-    constexpr int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
+    constexpr int W = kFootW - 2 * (K - 1), HO = R - 2 * (K - 1);
     static_assert(W > 0 && HO > 0, "tile too small for K steps");
     const int tyt = tile / A.tiles_x;
     const int txt = tile - tyt * A.tiles_x;
@@ -853,7 +853,7 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
     const int y = tyt * HO - (K - 1) + ly;
     const int n = A.n, P = A.plane;
     const bool inside = x >= 0 && x < n && y >= 0 && y < n;
-    const bool own = inside && lx >= K - 1 && lx <= kT2Width - K && ly >= K - 1 && ly <= R - K;
+    const bool own = inside && lx >= K - 1 && lx <= kFootW - K && ly >= K - 1 && ly <= R - K;
     const int m = *A.n0p + A.j;
     real lf[9], lg[5];
 #pragma unroll
@@ -866,14 +866,14 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
         adj_node<real>(A.fs, A.gs, A, x, y, lf, lg);
         if (own && x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = lf[i];
+        for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = lf[i];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = lg[i];
+        for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kFootW + lx] = lg[i];
     }
     __syncthreads();
 #pragma unroll
     for (int j = 2; j <= K; ++j) {
-        const bool act = inside && lx >= j - 1 && lx <= kT2Width - j && ly >= j - 1 && ly <= R - j;
+        const bool act = inside && lx >= j - 1 && lx <= kFootW - j && ly >= j - 1 && ly <= R - j;
         if (act) {
             const int mj = m - j + 1;
             adj_pull_lds<real, R>(lds, n, x, y, lx, ly,
@@ -885,9 +885,9 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
         __syncthreads();
         if (act) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = lf[i];
+            for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = lf[i];
 #pragma unroll
-            for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = lg[i];
+            for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kFootW + lx] = lg[i];
         }
         __syncthreads();
     }
@@ -900,9 +900,9 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
 }
 
 template <typename real, int R, int K>
-__global__ void __launch_bounds__(kT2Width * R) adjk_kernel(AdjArgs<real> A)
+__global__ void __launch_bounds__(kFootW * R) adjk_kernel(AdjArgs<real> A)
 {
-    __shared__ real lds[14 * R * kT2Width];
+    __shared__ real lds[14 * R * kFootW];
     const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
     if (tile >= A.tiles) return;
     adjk_tile<real, R, K>(A, lds, tile);
@@ -912,9 +912,9 @@ __global__ void __launch_bounds__(kT2Width * R) adjk_kernel(AdjArgs<real> A)
 // next-older one (every state stored) in one launch: workgroups
 // [0, A.tiles) take adjoint tiles, the rest forward tiles.
 template <typename real, int R, int K>
-__global__ void __launch_bounds__(kT2Width * R) adjk_fused_kernel(AdjArgs<real> A, StepArgs<real> F)
+__global__ void __launch_bounds__(kFootW * R) adjk_fused_kernel(AdjArgs<real> A, StepArgs<real> F)
 {
-    __shared__ real lds[14 * R * kT2Width];
+    __shared__ real lds[14 * R * kFootW];
     const int b = blockIdx.x;
     if (b < A.tiles) {
         adjk_tile<real, R, K>(A, lds, b);
@@ -1101,11 +1101,11 @@ __global__ void __launch_bounds__(256) nusselt_kernel(
 // left of and below the output tile) of one member each; phases as in
 // stepk_kernel, with two barriers per tile around the LDS reuse.
 template <typename real, int R, int K>
-__global__ void __launch_bounds__(kT2Width * R) batch_stepk_kernel(
+__global__ void __launch_bounds__(kFootW * R) batch_stepk_kernel(
     const CavityDev<real>* __restrict__ cavs, const TileRef* __restrict__ tiles, int t_begin,
     int t_end, int cur)
 {
-    __shared__ real lds[14 * R * kT2Width];
+    __shared__ real lds[14 * R * kFootW];
     const int lx = threadIdx.x, ly = threadIdx.y;
     for (int t = t_begin + blockIdx.x; t < t_end; t += gridDim.x) {
         const TileRef tr = tiles[t];
@@ -1114,7 +1114,7 @@ __global__ void __launch_bounds__(kT2Width * R) batch_stepk_kernel(
         const int x = tr.x0 + lx, y = tr.y0 + ly, n = cv.n;
         const bool inside = x >= 0 && x < n && y >= 0 && y < n;
         if (inside)
-            t2_phase1<real, R>(lds, cv.f[cur], cv.g[cur], cv.thw, n, cv.pitch, cv.plane, x, y, lx, ly, cv.c);
+            lds_first_phase<real, R>(lds, cv.f[cur], cv.g[cur], cv.thw, n, cv.pitch, cv.plane, x, y, lx, ly, cv.c);
         __syncthreads();
         real f[9], g[5];
 #pragma unroll
@@ -1123,23 +1123,23 @@ __global__ void __launch_bounds__(kT2Width * R) batch_stepk_kernel(
         for (int i = 0; i < 5; ++i) g[i] = real(0);
 #pragma unroll
         for (int j = 2; j < K; ++j) {
-            const bool act = inside && lx >= j - 1 && lx <= kT2Width - j && ly >= j - 1 && ly <= R - j;
+            const bool act = inside && lx >= j - 1 && lx <= kFootW - j && ly >= j - 1 && ly <= R - j;
             if (act) {
-                t2_gather_lds<real, R>(lds, cv.thw, n, x, y, lx, ly, cv.c, f, g);
+                gather_lds<real, R>(lds, cv.thw, n, x, y, lx, ly, cv.c, f, g);
                 real th, ux, uy;
                 collide<real>(f, g, cv.c, th, ux, uy);
             }
             __syncthreads();
             if (act) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kT2Width + lx] = f[i];
+                for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = f[i];
 #pragma unroll
-                for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kT2Width + lx] = g[i];
+                for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kFootW + lx] = g[i];
             }
             __syncthreads();
         }
-        if (inside && lx >= K - 1 && lx <= kT2Width - K && ly >= K - 1 && ly <= R - K)
-            t2_phase2<real, R>(lds, cv.f[cur ^ 1], cv.g[cur ^ 1], cv.thw, n, cv.pitch, cv.plane, x, y,
+        if (inside && lx >= K - 1 && lx <= kFootW - K && ly >= K - 1 && ly <= R - K)
+            lds_last_phase<real, R>(lds, cv.f[cur ^ 1], cv.g[cur ^ 1], cv.thw, n, cv.pitch, cv.plane, x, y,
                                lx, ly, cv.c);
         __syncthreads();                              // the next tile reuses the LDS
     }

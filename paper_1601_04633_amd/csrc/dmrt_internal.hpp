@@ -118,14 +118,14 @@ int launch_stepk(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
     A.fin = fin; A.gin = gin; A.fout = fout; A.gout = gout;
     A.thw = static_cast<const real*>(h->thw_real);
     A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
-    const int W = kT2Width - 2 * (K - 1), HO = R - 2 * (K - 1);
+    const int W = kFootW - 2 * (K - 1), HO = R - 2 * (K - 1);
     A.tiles_x = (h->n + W - 1) / W;
     A.tiles = A.tiles_x * ((h->n + HO - 1) / HO);
     A.xcd_remap = h->xcd_remap;
     A.c = make_coef<real>(h->p, h->d);
     int nblocks = A.tiles;
     if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
-    const dim3 grid(nblocks), block(kT2Width, R);
+    const dim3 grid(nblocks), block(kFootW, R);
 #define DMRT_KR(KK, RR)                                                                \
     if (K == KK && R == RR) {                                                           \
         hipLaunchKernelGGL((stepk_kernel<real, RR, KK>), grid, block, 0, s, A);         \

@@ -142,3 +142,24 @@ def test_sweep_shaped_batch_sampled_members():
         c = _single(members[i], "fp32", th[i], 200)
         assert np.array_equal(b.raw_state(i)[0], c.raw_state()[0]), i
         assert nu[i] == c.nusselt(0)[0]
+
+
+@pytest.mark.parametrize("temporal", [(1, 10), (2, 6), (4, 16)])
+def test_tiny_and_ragged_members_bitwise_equal_single(temporal):
+    """Members smaller than one footprint (4^2, 5^2) and ragged sizes beside
+    a larger one, K steps per launch: every member equals its single run."""
+    from paper_1601_04633_amd.dmrt import Batch
+    members = [dict(n=4, Ra=1e4, Pr=0.01), dict(n=5, Ra=3e3, Pr=0.005), dict(n=59, Ra=1e4, Pr=0.01),
+               dict(n=131, Ra=5e4, Pr=0.005)]
+    b = Batch(members, precision="fp32")
+    b.set_temporal(*temporal)
+    th = [inputs.theta_noise(m["n"], 70 + i, amp=1e-2) for i, m in enumerate(members)]
+    for i, t in enumerate(th):
+        b.set_theta(i, t)
+    b.step(77)
+    for i, m in enumerate(members):
+        c = _single(m, "fp32", th[i], 77)
+        fb, gb = b.raw_state(i)
+        fc, gc = c.raw_state()
+        assert np.array_equal(fb, fc) and np.array_equal(gb, gc), (i, m, temporal)
+    assert (b.status() == 0).all()
