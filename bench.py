@@ -293,18 +293,24 @@ def main():
     esz = 8 if prec == "fp64" else 4
     spl = temporal[0]                       # node updates per node per launch
     ms_launch = ms_step * spl
-    # algorithmic bytes of one launch: every population read and written once
-    # per launch, i.e. 28 words per node per launch, 28 / K words per node
-    # update when a launch advances K steps
-    alg_bytes = WORDS_PER_NODE * esz * n * n
+    # algorithmic bytes: the 28 words (112 B FP32) a node update must move
+    # (14 populations in, 14 out) times the node updates one launch makes
+    # (K n^2 when a launch advances K steps).  A K-step launch keeps K - 1 of
+    # its steps in LDS, so its HBM traffic is only the per-launch minimum of
+    # 28 words per node; that minimum and the measured counter bytes are
+    # reported beside it.
+    node_updates = spl * n * n
+    alg_bytes = WORDS_PER_NODE * esz * node_updates
     achieved = alg_bytes / (ms_launch * 1e-3) / 1e9
-    single_equiv = WORDS_PER_NODE * esz * n * n * spl / (ms_launch * 1e-3) / 1e9
+    min_bytes = WORDS_PER_NODE * esz * n * n
+    min_gbs = min_bytes / (ms_launch * 1e-3) / 1e9
     kname = (f"stepk_kernel<{'float' if esz == 4 else 'double'}, {temporal[1]}, {spl}>" if spl >= 2
              else f"step_kernel<{'float' if esz == 4 else 'double'}, 0>")
     traffic = measured_traffic(alg_bytes, kname) if n == 1024 and prec == "fp32" else None
     counters = counter_summary(kname) if n == 1024 and prec == "fp32" else None
-    log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic per launch "
-        f"({single_equiv:.1f} GB/s single-step equivalent), {ms_launch*1e3:.2f} us/launch, Nu {nu:.5f}")
+    log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic ({WORDS_PER_NODE * esz} B per node "
+        f"update), {min_gbs:.1f} GB/s of the per-launch HBM minimum, {ms_launch*1e3:.2f} us/launch, "
+        f"Nu {nu:.5f}")
 
     out = {
         "metric": METRIC,
@@ -327,11 +333,12 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "kernel": kname,
-                     "node_updates_per_launch": spl * n * n,
+                     "bytes_per_node_update": WORDS_PER_NODE * esz,
+                     "node_updates_per_launch": node_updates,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "bytes_per_node_update": WORDS_PER_NODE * esz // spl,
-                     "single_step_equivalent_GBs": round(single_equiv, 1),
-                     "single_step_equivalent_frac": round(single_equiv / HBM_PEAK_GBS, 4),
+                     "hbm_minimum_bytes_per_launch": min_bytes,
+                     "hbm_minimum_GBs": round(min_gbs, 1),
+                     "hbm_minimum_frac": round(min_gbs / HBM_PEAK_GBS, 4),
                      "valu_busy_frac_counters": None if counters is None else counters.get("valu_busy_frac")},
         "launch": {"block": list(launch[:2]), "xcd_remap": launch[2], "graph_steps": launch[3],
                    "steps_per_launch": spl, "tile_rows": temporal[1]},
@@ -363,15 +370,15 @@ def main():
         _, m64, l64, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1200), 600, launch,
                                      temporal=(4, 16))
         extras["fp64_four_step_R16_mlups"] = round(m64, 1)
-        extras["fp64_hbm_frac"] = round(224 / 4 * n * n / (l64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        extras["fp64_hbm_frac"] = round(m64 * 1e6 * 224 / 1e9 / HBM_PEAK_GBS, 4)
         _, m1, l1, _ = time_cavity(n, Ra, Pr, prec, max(args.steps // 5, 2000), 500, launch,
                                    temporal=(1, 10))
         extras["fp32_single_step_mlups"] = round(m1, 1)
-        extras["fp32_single_step_hbm_frac"] = round(112 * n * n / (l1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        extras["fp32_single_step_hbm_frac"] = round(m1 * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4)
         log("extra: 2048^2 fp32 control (state larger than the 256 MB last-level cache)")
         _, m2k, l2k, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=(4, 16))
         extras["fp32_2048_four_step_R16_mlups"] = round(m2k, 1)
-        extras["fp32_2048_hbm_frac"] = round(112 / 4 * 2048 * 2048 / (l2k * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        extras["fp32_2048_hbm_frac"] = round(m2k * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4)
         out["extras"] = extras
     if "batch" in sections:
         log("batch: 64-cavity Ra x Pr sweep vs one by one")
