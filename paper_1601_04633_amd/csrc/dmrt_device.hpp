@@ -860,10 +860,21 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
     for (int i = 0; i < 9; ++i) lf[i] = real(0);
 #pragma unroll
     for (int i = 0; i < 5; ++i) lg[i] = real(0);
+    // the forward state each phase linearises about does not depend on mu:
+    // the gather for phase j + 1 is issued before the work of phase j, so
+    // one gather is always in flight (registers sf, sg hold the next one)
+    real cf[9], cg[5], sf[9], sg[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { cf[i] = real(0); sf[i] = real(0); }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { cg[i] = real(0); sg[i] = real(0); }
+    if (inside) gather<real, BC_CAVITY>(A.fs, A.gs, A.thw, n, A.pitch, P, x, y, A.c, cf, cg);
+    if (K >= 2 && inside && lx >= 1 && lx <= kFootW - 2 && ly >= 1 && ly <= R - 2)
+        gather<real, BC_CAVITY>(A.fs - A.slot, A.gs - A.slot, A.thw, n, A.pitch, P, x, y, A.c, sf, sg);
     if (inside) {
         adj_pull<real>(A.lin, n, A.pitch, P, x, y, adj_seed_at<real>(x, m >= A.win_start, A.seed0, A.seed1),
                        lf, lg);
-        adj_node<real>(A.fs, A.gs, A, x, y, lf, lg);
+        collide_vjp<real>(cf, cg, A.c, lf, lg);
         if (own && x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
 #pragma unroll
         for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = lf[i];
@@ -874,11 +885,18 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
 #pragma unroll
     for (int j = 2; j <= K; ++j) {
         const bool act = inside && lx >= j - 1 && lx <= kFootW - j && ly >= j - 1 && ly <= R - j;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) cf[i] = sf[i];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) cg[i] = sg[i];
+        if (j < K && inside && lx >= j && lx <= kFootW - j - 1 && ly >= j && ly <= R - j - 1)
+            gather<real, BC_CAVITY>(A.fs - j * A.slot, A.gs - j * A.slot, A.thw, n, A.pitch, P, x, y, A.c,
+                                    sf, sg);
         if (act) {
             const int mj = m - j + 1;
             adj_pull_lds<real, R>(lds, n, x, y, lx, ly,
                                   adj_seed_at<real>(x, mj >= A.win_start, A.seed0, A.seed1), lf, lg);
-            adj_node<real>(A.fs - (j - 1) * A.slot, A.gs - (j - 1) * A.slot, A, x, y, lf, lg);
+            collide_vjp<real>(cf, cg, A.c, lf, lg);
             if (own && x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
         }
         if (j == K) break;
