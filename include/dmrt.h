@@ -225,9 +225,9 @@ int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
  * steps on its 64 x tile_rows footprint, shrinking by one node per step, and
  * keeps them in LDS; every population is read and written once per launch,
  * so HBM traffic per node update drops from 28 to about 28/K words plus
- * halo).  tile_rows in {4, 6, 10, 16} for K <= 2, {6, 10, 16} for K = 3,
- * {10, 16} for K = 4.  K >= 2 is available for DMRT_BC_CAVITY only (EINVAL
- * otherwise).  Results are identical to single steps; Nusselt samples are
+ * halo).  tile_rows in {4, 6, 10, 16} for K <= 2, {6, 10, 12, 14, 16} for
+ * K = 3, {10, 12, 14, 16} for K = 4.  K >= 2 is available for
+ * DMRT_BC_CAVITY only (EINVAL otherwise).  Results are identical to single steps; Nusselt samples are
  * still taken after every stride-th step. */
 int dmrt_set_temporal(dmrt_cavity *h, int steps_per_launch, int tile_rows);
 

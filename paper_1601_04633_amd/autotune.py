@@ -26,7 +26,7 @@ CACHE_PATH = os.environ.get("DMRT_AUTOTUNE_CACHE",
 MB = 1 << 20
 
 BATCH_SPACE = {
-    "temporal": [(4, 16), (3, 16), (2, 6), (2, 10), (3, 10), (4, 10), (1, 10)],
+    "temporal": [(4, 16), (4, 12), (3, 16), (3, 12), (2, 6), (2, 10), (3, 10), (4, 10), (1, 10)],
     "block": [(64, 4), (64, 2), (64, 8), (128, 2), (128, 4), (256, 1), (64, 1)],
     "order": [1, 0, 2],
     "grid_blocks": [0, 4096, 16384],
@@ -37,7 +37,7 @@ BATCH_DEFAULT = {"temporal": (4, 16), "block": (64, 4), "order": 1, "grid_blocks
                  "group": (0, 64)}
 
 CAVITY_SPACE = {
-    "temporal": [(4, 16), (3, 16), (3, 10), (2, 6), (2, 10), (4, 10), (1, 10)],
+    "temporal": [(4, 16), (4, 12), (3, 16), (3, 12), (3, 10), (2, 6), (2, 10), (4, 10), (1, 10)],
     "block": [(256, 1), (128, 2), (64, 4), (512, 1), (128, 1), (64, 1), (256, 2)],
     "xcd_remap": [1, 0],
 }
@@ -209,7 +209,7 @@ def tune_cavity(cavity, stream_ptr=None, steps=256, use_cache=True, verbose=Fals
     return best, best_t, trials
 
 
-ADJOINT_SPACE = [(4, 16), (3, 10), (2, 6), (2, 10), (2, 16), (3, 16), (4, 10), (1, 10)]
+ADJOINT_SPACE = [(4, 16), (4, 12), (3, 12), (3, 10), (2, 6), (2, 10), (3, 16), (4, 10), (1, 10)]
 
 
 def tune_adjoint(cavity, nsteps=2000, avg_last=400, ckpt_every=500, stream_ptr=None, use_cache=True,

@@ -233,9 +233,7 @@ int launch_adjk(const dmrt_cavity* h, hipStream_t s, const AdjArgs<real>* A, con
                                dim3(F->xcd_remap ? padded(F->tiles) : F->tiles), block, 0, s, *F, slot); \
         return record_hip(hipGetLastError(), "adjoint K-step kernel");                                 \
     }
-    DMRT_AKR(2, 4) DMRT_AKR(2, 6) DMRT_AKR(2, 10) DMRT_AKR(2, 16)
-    DMRT_AKR(3, 6) DMRT_AKR(3, 10) DMRT_AKR(3, 16)
-    DMRT_AKR(4, 10) DMRT_AKR(4, 16)
+    DMRT_FOR_EACH_KR(DMRT_AKR)
 #undef DMRT_AKR
     return DMRT_EINVAL;
 }

@@ -259,9 +259,7 @@ int launch_rangek_t(dmrt_batch* b, hipStream_t s, int t0, int t1, int from)
         HIPCHK(hipGetLastError());                                                                    \
         return DMRT_OK;                                                                               \
     }
-    DMRT_BKR(2, 4) DMRT_BKR(2, 6) DMRT_BKR(2, 10) DMRT_BKR(2, 16)
-    DMRT_BKR(3, 6) DMRT_BKR(3, 10) DMRT_BKR(3, 16)
-    DMRT_BKR(4, 10) DMRT_BKR(4, 16)
+    DMRT_FOR_EACH_KR(DMRT_BKR)
 #undef DMRT_BKR
     return DMRT_EINVAL;
 }

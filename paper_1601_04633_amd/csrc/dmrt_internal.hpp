@@ -98,12 +98,19 @@ struct dmrt_cavity {
 namespace dmrt {
 
 // Valid (steps per launch, footprint rows) pairs of stepk_kernel.
+// The (steps per launch K, footprint rows R) pairs the K-step kernels are
+// built for; every launcher instantiates its kernels over this one list.
+#define DMRT_FOR_EACH_KR(X)                                                     \
+    X(2, 4) X(2, 6) X(2, 10) X(2, 16)                                          \
+    X(3, 6) X(3, 10) X(3, 12) X(3, 14) X(3, 16)                                \
+    X(4, 10) X(4, 12) X(4, 14) X(4, 16)
+
 inline bool valid_temporal(int k, int rows)
 {
     if (k == 1) return rows == 4 || rows == 6 || rows == 10 || rows == 16;
-    if (k == 2) return rows == 4 || rows == 6 || rows == 10 || rows == 16;
-    if (k == 3) return rows == 6 || rows == 10 || rows == 16;
-    if (k == 4) return rows == 10 || rows == 16;
+#define DMRT_KR_OK(KK, RR) if (k == KK && rows == RR) return true;
+    DMRT_FOR_EACH_KR(DMRT_KR_OK)
+#undef DMRT_KR_OK
     return false;
 }
 
@@ -131,9 +138,7 @@ int launch_stepk(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
         hipLaunchKernelGGL((stepk_kernel<real, RR, KK>), grid, block, 0, s, A);         \
         return record_hip(hipGetLastError(), "stepk_kernel");                          \
     }
-    DMRT_KR(2, 4) DMRT_KR(2, 6) DMRT_KR(2, 10) DMRT_KR(2, 16)
-    DMRT_KR(3, 6) DMRT_KR(3, 10) DMRT_KR(3, 16)
-    DMRT_KR(4, 10) DMRT_KR(4, 16)
+    DMRT_FOR_EACH_KR(DMRT_KR)
 #undef DMRT_KR
     return DMRT_EINVAL;
 }

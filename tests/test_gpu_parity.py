@@ -279,8 +279,8 @@ def test_case1_physics_against_paper():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("k,rows", [(2, 4), (2, 6), (2, 10), (2, 16), (3, 6), (3, 10), (3, 16),
-                                    (4, 10), (4, 16)])
+@pytest.mark.parametrize("k,rows", [(2, 4), (2, 6), (2, 10), (2, 16), (3, 6), (3, 10), (3, 12),
+                                    (3, 14), (3, 16), (4, 10), (4, 12), (4, 14), (4, 16)])
 def test_multi_step_launch_equals_single_steps(precision, k, rows):
     """K steps per launch through LDS give bitwise the state of single
     steps, for ragged sizes, odd step counts, graph replay and Nu sampling
