@@ -242,7 +242,10 @@ def tune_adjoint(cavity, nsteps=2000, avg_last=400, ckpt_every=500, stream_ptr=N
     return best, best_t, trials
 
 
+GRAPH_STEPS = 60       # steps per captured graph: a multiple of every K in 1..4
+
+
 def apply_cavity(cavity, cfg):
     """Applies a single-cavity launch configuration (see CAVITY_SPACE)."""
-    cavity.set_launch(cfg["block"][0], cfg["block"][1], cfg["xcd_remap"], 64)
+    cavity.set_launch(cfg["block"][0], cfg["block"][1], cfg["xcd_remap"], GRAPH_STEPS)
     cavity.set_temporal(cfg["temporal"][0], cfg["temporal"][1])
