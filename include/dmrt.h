@@ -215,8 +215,9 @@ int dmrt_load_state(dmrt_cavity *h, const void *host, size_t bytes);
 /* Launch shape of the step kernel: block_x in {64, 128, 256, 512},
  * block_y >= 1 with block_x * block_y <= 1024, xcd_remap 0/1 (assign
  * contiguous tiles to each of the 8 accelerator dies), graph_steps >= 0
- * (steps per captured graph; 0 = never capture).  Defaults are set at
- * creation; results do not depend on the launch shape. */
+ * (steps per captured graph; 0 = never capture).  Defaults at creation:
+ * 256 x 1, die-aware order, graphs of 60 steps (a multiple of every
+ * steps-per-launch K).  Results do not depend on the launch shape. */
 int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
                     int graph_steps);
 

@@ -76,7 +76,7 @@ struct dmrt_cavity {
     long ring_cap = 0;
     int series_stride = 0;
     // launch
-    int block_x = 256, block_y = 1, xcd_remap = 1, graph_steps = 64;
+    int block_x = 256, block_y = 1, xcd_remap = 1, graph_steps = 60;   // 60: a multiple of every K
     int temporal = 1, t_rows = 10;    // steps per launch (1, or 2..4 through LDS) and its tile rows
     int adj_temporal = 1, adj_rows = 10;   // the same for the adjoint's backward launches
     int graph_flips[2] = {0, 0};      // copy changes made by one replay of graph[p]
