@@ -199,9 +199,6 @@ __device__ __forceinline__ int tile_of_block(int bid, int nblocks, int remap)
     return (bid & 7) * per + (bid >> 3);
 }
 
-// Pull-streaming with the wall rules (row a1): f_i(r) = f*_i(r - e_i) when
-// r - e_i is inside, else the halfway bounce-back f*_opp(i)(r); for g the
-// same, with Eq. 44 on adiabatic walls and Eq. 45 on the isothermal walls.
 // Element at byte offset `b` from `base`: a uniform base pointer and a
 // 32-bit per-lane offset, so a load needs no 64-bit address arithmetic.
 template <typename real>
@@ -215,6 +212,9 @@ __device__ __forceinline__ void stb(real* __restrict__ base, unsigned b, real v)
     *reinterpret_cast<real*>(reinterpret_cast<char*>(base) + b) = v;
 }
 
+// Pull-streaming with the wall rules (Eq. 25, Eqs. 44-45): f_i(r) = f*_i(r - e_i) when
+// r - e_i is inside, else the halfway bounce-back f*_opp(i)(r); for g the
+// same, with Eq. 44 on adiabatic walls and Eq. 45 on the isothermal walls.
 template <typename real, int BC>
 __device__ __forceinline__ void gather(const real* __restrict__ fi, const real* __restrict__ gi,
                                        const real* __restrict__ thw, int n, int pitch, int P,
@@ -276,7 +276,7 @@ __device__ __forceinline__ void gather(const real* __restrict__ fi, const real* 
     }
 }
 
-// One node update (rows a1-a5): gather from the current copy with the wall
+// One node update (Eqs. 25-45): gather from the current copy with the wall
 // rules, collide in registers, store into the other copy.  Returns the
 // node's temperature sum of the stored g* in FP64 (used only by the
 // Nusselt-accumulating variant; dead code elsewhere).
