@@ -147,7 +147,7 @@ class Reference:
                           requires_grad=True)
         J = self.objective(tw, t0, N, K, segment)
         gw, g0 = torch.autograd.grad(J, (tw, t0))
-        return float(J), gw.numpy(), g0.numpy()
+        return float(J.detach()), gw.numpy(), g0.numpy()
 
     def fields_after(self, theta_w, theta0, N):
         with torch.no_grad():
