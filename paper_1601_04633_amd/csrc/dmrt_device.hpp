@@ -628,12 +628,6 @@ static __global__ void __launch_bounds__(256) sum_kernel(const double* __restric
 // instead of 28 (the footprint ring's re-reads hit L2).
 constexpr int kFootW = 64;         // footprint width (one wavefront)
 
-template <typename real, int R>
-__device__ __forceinline__ real lds_at(const real* lds, int q, int ly, int lx)
-{
-    return lds[(q * R + ly) * kFootW + lx];
-}
-
 // First phase of the K-step update: s(t+1) at footprint node (x, y) into LDS.
 template <typename real, int R>
 __device__ __forceinline__ void lds_first_phase(real* lds, const real* __restrict__ fi,
