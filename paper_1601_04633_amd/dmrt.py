@@ -340,11 +340,11 @@ class Cavity:
     def adjoint_release(self):
         check(dmrt_adjoint_release(self._h), "dmrt_adjoint_release")
 
-    def adjoint_set_temporal(self, steps_per_launch=2, tile_rows=10):
+    def adjoint_set_temporal(self, steps_per_launch=4, tile_rows=16):
         check(dmrt_adjoint_set_temporal(self._h, steps_per_launch, tile_rows),
               "dmrt_adjoint_set_temporal")
 
-    def set_temporal(self, steps_per_launch=2, tile_rows=10):
+    def set_temporal(self, steps_per_launch=4, tile_rows=16):
         check(dmrt_set_temporal(self._h, steps_per_launch, tile_rows), "dmrt_set_temporal")
 
     def buffers(self):
@@ -410,7 +410,7 @@ class Batch:
         check(dmrt_batch_set_schedule(self._h, block_x, block_y, order, grid_blocks,
                                       int(group_bytes), group_steps), "dmrt_batch_set_schedule")
 
-    def set_temporal(self, steps_per_launch=2, tile_rows=10):
+    def set_temporal(self, steps_per_launch=4, tile_rows=16):
         check(dmrt_batch_set_temporal(self._h, steps_per_launch, tile_rows), "dmrt_batch_set_temporal")
 
     def step(self, nsteps=1):
