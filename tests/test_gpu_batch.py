@@ -163,3 +163,30 @@ def test_tiny_and_ragged_members_bitwise_equal_single(temporal):
         fc, gc = c.raw_state()
         assert np.array_equal(fb, fc) and np.array_equal(gb, gc), (i, m, temporal)
     assert (b.status() == 0).all()
+
+
+def test_sweep_in_benchmark_schedule_sampled_members():
+    """The 64-cavity sweep in a schedule of the kind the benchmark's tuner
+    picks (four steps per launch on 64 x 16 footprints, a persistent grid of
+    16,384 workgroups, 224 MB cavity groups of 32 steps): sampled members of
+    every side equal their single runs bitwise."""
+    from paper_1601_04633_amd.dmrt import Batch
+    specs = inputs.batch_cavities(64, 4633)
+    members = [dict(n=s, Ra=ra, Pr=pr) for s, ra, pr in specs]
+    b = Batch(members, precision="fp32")
+    b.set_schedule(block_x=128, block_y=2, order=1, grid_blocks=16384, group_bytes=224 << 20,
+                   group_steps=32)
+    b.set_temporal(4, 16)
+    th = {}
+    for i, m in enumerate(members):
+        th[i] = inputs.theta_noise(m["n"], 4633 + i)
+        b.set_theta(i, th[i])
+    b.step(224)
+    nu = b.nusselt()
+    assert np.all(np.isfinite(nu))
+    sides = [m["n"] for m in members]
+    picks = {sides.index(s) for s in set(sides)} | {len(members) - 1}
+    for i in sorted(picks):
+        c = _single(members[i], "fp32", th[i], 224)
+        assert np.array_equal(b.raw_state(i)[0], c.raw_state()[0]), i
+        assert nu[i] == c.nusselt(0)[0]

@@ -318,3 +318,31 @@ def test_two_step_rejected_outside_cavity():
     c = Cavity(n=32, Ra=1e4, Pr=0.01, bc_mode=1)
     with pytest.raises(DmrtError):
         c.set_temporal(2, 10)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_full_size_centro_symmetry_in_benchmark_shape(precision):
+    """1024^2, Ra 1e5, Pr 0.001 in the benchmark's launch shape (four steps
+    per launch, 64 x 16 footprints, die-aware order, graphs of 60 steps),
+    4,000 steps from theta = 0: rotating the cavity by 180 degrees and
+    flipping theta maps the problem onto itself, so theta, U, V stay
+    antisymmetric and P symmetric at full size (a property that holds at
+    any size, where the oracle cannot follow)."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    print(f"[parity] 1024^2 centro-symmetry {precision}", flush=True)
+    n = 1024
+    c = Cavity(n=n, Ra=1e5, Pr=0.001, precision=precision)
+    c.set_launch(256, 1, 1, 60)
+    c.set_temporal(4, 16)
+    c.set_theta(np.zeros((n, n)))
+    c.step(4000)
+    U, V, T, P = c.fields()
+    c.close()
+    R = lambda A: A[::-1, ::-1]
+    tol = 1e-6 if precision == "fp32" else 1e-13
+    assert np.abs(T + R(T)).max() <= tol * np.abs(T).max()
+    assert np.abs(U + R(U)).max() <= tol * np.abs(U).max()
+    assert np.abs(V + R(V)).max() <= tol * np.abs(V).max()
+    assert np.abs(P - R(P)).max() <= tol * np.abs(P).max()
+    # the boundary layers have formed: rising at the hot wall, sinking at the cold
+    assert V[n // 2, 0] > 0 and V[n // 2, n - 1] < 0 and np.abs(U).max() > 1e-5
