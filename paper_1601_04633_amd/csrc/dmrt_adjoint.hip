@@ -124,7 +124,8 @@ template <typename real>
 real* cur_g(dmrt_cavity* h, int copy) { return static_cast<real*>(h->gbuf) + (size_t)copy * 5 * h->plane; }
 
 // `count` forward steps on the cavity's ping-pong copies starting at `from`;
-// plain steps go K per launch when the handle's launch shape says so.
+// steps go K per launch when the handle's launch shape says so (with the
+// Nusselt sums of the objective window accumulated in the same launches).
 // *flips receives the number of launches (copy changes).
 template <typename real>
 int enqueue_fwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, int from, long count, bool nu,
@@ -134,9 +135,10 @@ int enqueue_fwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, int from, long c
     long i = 0;
     while (i < count) {
         int rc;
-        if (!nu && h->temporal >= 2 && i + h->temporal <= count) {
+        if (h->temporal >= 2 && i + h->temporal <= count) {
             rc = launch_stepk<real>(h, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),
-                                    cur_g<real>(h, c ^ 1));
+                                    cur_g<real>(h, c ^ 1), nu ? h->thw_dbl : nullptr,
+                                    nu ? a->nu_acc : nullptr);
             i += h->temporal;
         } else {
             rc = launch_fwd<real>(h, a, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),

@@ -709,8 +709,27 @@ __device__ __forceinline__ void lds_last_phase(const real* lds, real* __restrict
 // every intermediate state is also stored on the output tile (a partition
 // of the domain), state t + j at fout/gout + (j - 1) * slot: the adjoint's
 // recompute keeps every state of a segment.
-template <typename real, int R, int K, bool ALL>
-__device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, int tile, long slot)
+// With NU, every step of the launch also adds its hot-wall Nusselt sum
+// 8 theta_w - 9 theta(0, y) + theta(1, y) (Eqs. 18-19) to acc[y], in FP64
+// and in the same order and arithmetic as step_nu_kernel; the x = 0 and
+// x = 1 nodes are neighbouring lanes of one wavefront.
+template <typename real>
+__device__ __forceinline__ void nu_row_add(const real (&g)[5], bool have, bool wall_lane, int y,
+                                           const double* __restrict__ thw_d, double* __restrict__ acc)
+{
+    double ts = 0.0;
+    if (have) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) ts += double(g[i]);
+    }
+    const double ts1 = __shfl_down(ts, 1, 64);
+    if (wall_lane) acc[y] += 8.0 * thw_d[y] - 9.0 * ts + ts1;
+}
+
+template <typename real, int R, int K, bool ALL, bool NU = false>
+__device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, int tile, long slot,
+                                           const double* __restrict__ thw_d = nullptr,
+                                           double* __restrict__ acc = nullptr)
 {
     constexpr int W = kFootW - 2 * (K - 1), HO = R - 2 * (K - 1);
     static_assert(W > 0 && HO > 0, "tile too small for K steps");
@@ -742,6 +761,7 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
             for (int i = 0; i < 5; ++i) A.gout[i * P + k] = g[i];
         }
     }
+    if constexpr (NU) nu_row_add<real>(g, inside, own && x == 0, y, thw_d, acc);
     __syncthreads();
 #pragma unroll
     for (int j = 2; j < K; ++j) {
@@ -751,6 +771,7 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
             real th, ux, uy;
             collide<real>(f, g, A.c, th, ux, uy);
         }
+        if constexpr (NU) nu_row_add<real>(g, act, own && x == 0, y, thw_d, acc);
         __syncthreads();
         if (act) {
 #pragma unroll
@@ -768,6 +789,21 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
         }
         __syncthreads();
     }
+    if constexpr (NU) {
+        // last phase with every lane present for the wavefront shuffle
+        if (own) {
+            gather_lds<real, R>(lds, A.thw, n, x, y, lx, ly, A.c, f, g);
+            real th, ux, uy;
+            collide<real>(f, g, A.c, th, ux, uy);
+            const unsigned kb = unsigned(k) * sizeof(real), Pb = unsigned(P) * sizeof(real);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) stb(A.fout, kb + i * Pb, f[i]);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) stb(A.gout, kb + i * Pb, g[i]);
+        }
+        nu_row_add<real>(g, own, own && x == 0, y, thw_d, acc);
+        return;
+    }
     if (!own) return;
     const long last = ALL ? (K - 1) * slot : 0;
     lds_last_phase<real, R>(lds, A.fout + last, A.gout + last, A.thw, n, A.pitch, P, x, y, lx, ly, A.c);
@@ -780,6 +816,18 @@ __global__ void __launch_bounds__(kFootW * R) stepk_kernel(StepArgs<real> A)
     const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
     if (tile >= A.tiles) return;                      // uniform per workgroup
     stepk_tile<real, R, K, false>(A, lds, tile, 0);
+}
+
+// K steps per launch that also accumulate the hot-wall Nusselt sums
+// (the objective window of the adjoint's forward run).
+template <typename real, int R, int K>
+__global__ void __launch_bounds__(kFootW * R) stepk_nu_kernel(StepArgs<real> A, const double* __restrict__ thw_d,
+                                                              double* __restrict__ acc)
+{
+    __shared__ real lds[14 * R * kFootW];
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;
+    stepk_tile<real, R, K, false, true>(A, lds, tile, 0, thw_d, acc);
 }
 
 // K forward steps storing every state (the adjoint's recompute on its own).

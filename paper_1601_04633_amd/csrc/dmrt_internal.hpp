@@ -115,10 +115,12 @@ inline bool valid_temporal(int k, int rows)
 }
 
 // Launches K = h->temporal steps of the cavity from (fin, gin) to (fout, gout)
-// through LDS with footprint rows h->t_rows (K >= 2).
+// through LDS with footprint rows h->t_rows (K >= 2).  With acc non-null the
+// launch also adds each step's hot-wall Nusselt row sums to acc (FP64, n
+// entries; thw_d the FP64 wall temperatures).
 template <typename real>
 int launch_stepk(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
-                 real* gout)
+                 real* gout, const double* thw_d = nullptr, double* acc = nullptr)
 {
     const int K = h->temporal, R = h->t_rows;
     StepArgs<real> A;
@@ -133,10 +135,14 @@ int launch_stepk(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
     int nblocks = A.tiles;
     if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
     const dim3 grid(nblocks), block(kFootW, R);
-#define DMRT_KR(KK, RR)                                                                \
-    if (K == KK && R == RR) {                                                           \
-        hipLaunchKernelGGL((stepk_kernel<real, RR, KK>), grid, block, 0, s, A);         \
-        return record_hip(hipGetLastError(), "stepk_kernel");                          \
+#define DMRT_KR(KK, RR)                                                                   \
+    if (K == KK && R == RR) {                                                              \
+        if (acc) {                                                                         \
+            hipLaunchKernelGGL((stepk_nu_kernel<real, RR, KK>), grid, block, 0, s, A, thw_d, acc); \
+            return record_hip(hipGetLastError(), "stepk_nu_kernel");                      \
+        }                                                                                  \
+        hipLaunchKernelGGL((stepk_kernel<real, RR, KK>), grid, block, 0, s, A);            \
+        return record_hip(hipGetLastError(), "stepk_kernel");                             \
     }
     DMRT_FOR_EACH_KR(DMRT_KR)
 #undef DMRT_KR
