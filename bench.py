@@ -35,11 +35,15 @@ TRAFFIC_FILES = {
     "step_kernel<float, 0>": os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json"),
     "stepk_kernel<float, 16, 4>": os.path.join(ROOT, "profiles",
                                                "stepk_kernel_K4_R16_cavity_1024_fp32_traffic.json"),
+    "stepm_kernel<float, 4, 3, true>": os.path.join(ROOT, "profiles",
+                                                    "stepm_kernel_K4_B3_cavity_1024_fp32_traffic.json"),
 }
 # launch configuration timed by default (the fastest for this workload on
 # MI355X): four steps per launch through LDS, 64 x 16 footprints,
 # die-aware tile order, graphs of 60 steps
-DEFAULT_TEMPORAL = (4, 16)
+# four steps per launch, workgroups of 4 x 3 wavefronts marching up chunks
+# of rows (chunk length chosen to keep one launch resident)
+DEFAULT_TEMPORAL = ("march", 4, 3, 0)
 DEFAULT_LAUNCH = (256, 1, 1, 60)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_04633_amd", "csrc", f)
                   for f in ("dmrt_device.hpp",)]
@@ -82,9 +86,41 @@ def measured_traffic(bytes_alg_per_launch, kernel):
     return None if t is None else t.get("bytes_per_launch")
 
 
-def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601, temporal=None):
+def parse_temporal(text):
+    """'K,R' (tile kernel) or 'march,K,B[,chunk]' (row-marching kernel)."""
+    parts = text.split(",")
+    if parts[0] == "march":
+        vals = [int(v) for v in parts[1:]]
+        return ("march", vals[0], vals[1], vals[2] if len(vals) > 2 else 0)
+    return tuple(int(v) for v in parts)
+
+
+def steps_per_launch(temporal):
+    return temporal[1] if temporal[0] == "march" else temporal[0]
+
+
+def kernel_name(temporal, esz):
+    t = "float" if esz == 4 else "double"
+    if temporal[0] == "march":
+        return f"stepm_kernel<{t}, {temporal[1]}, {temporal[2]}, true>"
+    if temporal[0] >= 2:
+        return f"stepk_kernel<{t}, {temporal[1]}, {temporal[0]}>"
+    return f"step_kernel<{t}, 0>"
+
+
+def apply_temporal(c, temporal):
+    """Sets the cavity's steps per launch; returns the rows per workgroup of
+    the row-marching kernel (None for the tile kernel)."""
+    if temporal[0] == "march":
+        return c.set_temporal_march(temporal[1], temporal[2], temporal[3])
+    c.set_temporal(*temporal)
+    return None
+
+
+def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601, temporal=None, info=None):
     """Returns (ms total, MLUPS, avg ms per step, Nu) for `steps` steps timed
-    with HIP events on the cavity's own stream."""
+    with HIP events on the cavity's own stream; info (a dict) receives the
+    chunk rows of the row-marching kernel."""
     import torch
     from paper_1601_04633_amd import inputs
     from paper_1601_04633_amd.dmrt import Cavity
@@ -93,7 +129,9 @@ def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601, tem
     if launch:
         c.set_launch(*launch)
     if temporal:
-        c.set_temporal(*temporal)
+        chunk = apply_temporal(c, temporal)
+        if info is not None:
+            info["chunk_rows"] = chunk
     c.set_theta(inputs.theta_noise(n, seed))
     c.step(warmup)
     c.sync()
@@ -267,7 +305,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,xcd_remap,graph_steps")
-    ap.add_argument("--temporal", default="", help="steps_per_launch,tile_rows (default 4,16)")
+    ap.add_argument("--temporal", default="",
+                    help="steps_per_launch,tile_rows or march,steps_per_launch,group_rows[,chunk_rows] "
+                         "(default march,4,3)")
     ap.add_argument("--sections", default="main,extras,batch,adjoint,cpu",
                     help="comma list of main, extras, batch, adjoint, cpu")
     ap.add_argument("--batch-steps", type=int, default=5000)
@@ -289,15 +329,16 @@ def main():
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
 
     n, Ra, Pr, prec = args.n, args.Ra, args.Pr, args.precision
-    temporal = tuple(int(v) for v in args.temporal.split(",")) if args.temporal else DEFAULT_TEMPORAL
+    temporal = parse_temporal(args.temporal) if args.temporal else DEFAULT_TEMPORAL
     if launch is None:
         launch = DEFAULT_LAUNCH
     log(f"main: {n}^2 Ra={Ra:g} Pr={Pr:g} {prec} steps={args.steps} warmup={args.warmup} "
-        f"launch={launch} steps/launch,rows={temporal}")
+        f"launch={launch} temporal={temporal}")
+    info = {}
     ms, mlups, ms_step, nu = time_cavity(n, Ra, Pr, prec, args.steps, args.warmup, launch,
-                                         temporal=temporal)
+                                         temporal=temporal, info=info)
     esz = 8 if prec == "fp64" else 4
-    spl = temporal[0]                       # node updates per node per launch
+    spl = steps_per_launch(temporal)        # node updates per node per launch
     ms_launch = ms_step * spl
     # algorithmic bytes: the 28 words (112 B FP32) a node update must move
     # (14 populations in, 14 out) times the node updates one launch makes
@@ -310,8 +351,7 @@ def main():
     achieved = alg_bytes / (ms_launch * 1e-3) / 1e9
     min_bytes = WORDS_PER_NODE * esz * n * n
     min_gbs = min_bytes / (ms_launch * 1e-3) / 1e9
-    kname = (f"stepk_kernel<{'float' if esz == 4 else 'double'}, {temporal[1]}, {spl}>" if spl >= 2
-             else f"step_kernel<{'float' if esz == 4 else 'double'}, 0>")
+    kname = kernel_name(temporal, esz)
     traffic = measured_traffic(alg_bytes, kname) if n == 1024 and prec == "fp32" else None
     counters = counter_summary(kname) if n == 1024 and prec == "fp32" else None
     log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic ({WORDS_PER_NODE * esz} B per node "
@@ -347,7 +387,10 @@ def main():
                      "hbm_minimum_frac": round(min_gbs / HBM_PEAK_GBS, 4),
                      "valu_busy_frac_counters": None if counters is None else counters.get("valu_busy_frac")},
         "launch": {"block": list(launch[:2]), "xcd_remap": launch[2], "graph_steps": launch[3],
-                   "steps_per_launch": spl, "tile_rows": temporal[1]},
+                   "steps_per_launch": spl,
+                   **({"kernel": "row-marching", "group_rows": temporal[2],
+                       "chunk_rows": info.get("chunk_rows")} if temporal[0] == "march"
+                      else {"kernel": "tile", "tile_rows": temporal[1]})},
         "nu_hot_wall": nu,
     }
 
@@ -372,19 +415,28 @@ def main():
 
     if "extras" in sections:
         extras = {}
-        log("extra: fp64 same cavity")
-        _, m64, l64, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1200), 600, launch,
-                                     temporal=(4, 16))
-        extras["fp64_four_step_R16_mlups"] = round(m64, 1)
-        extras["fp64_hbm_frac"] = round(m64 * 1e6 * 224 / 1e9 / HBM_PEAK_GBS, 4)
-        _, m1, l1, _ = time_cavity(n, Ra, Pr, prec, max(args.steps // 5, 2000), 500, launch,
-                                   temporal=(1, 10))
+        log("extra: fp64 same cavity, row-marching (4 steps, 4 x 4 wavefronts) and tile (4 steps, 16 rows)")
+        _, m64, _, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1200), 600, launch,
+                                   temporal=("march", 4, 4, 0))
+        extras["fp64_march_K4_B4_mlups"] = round(m64, 1)
+        extras["fp64_march_algorithmic_hbm_frac"] = round(m64 * 1e6 * 224 / 1e9 / HBM_PEAK_GBS, 4)
+        _, m64t, _, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1200), 600, launch,
+                                    temporal=(4, 16))
+        extras["fp64_tile_K4_R16_mlups"] = round(m64t, 1)
+        log("extra: fp32 tile kernel (4 steps, 16 rows) and single steps")
+        _, mt, _, _ = time_cavity(n, Ra, Pr, prec, max(args.steps // 5, 2000), 500, launch,
+                                  temporal=(4, 16))
+        extras["fp32_tile_K4_R16_mlups"] = round(mt, 1)
+        _, m1, _, _ = time_cavity(n, Ra, Pr, prec, max(args.steps // 5, 2000), 500, launch,
+                                  temporal=(1, 10))
         extras["fp32_single_step_mlups"] = round(m1, 1)
         extras["fp32_single_step_hbm_frac"] = round(m1 * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4)
         log("extra: 2048^2 fp32 control (state larger than the 256 MB last-level cache)")
-        _, m2k, l2k, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=(4, 16))
-        extras["fp32_2048_four_step_R16_mlups"] = round(m2k, 1)
-        extras["fp32_2048_hbm_frac"] = round(m2k * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4)
+        _, m2k, _, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=("march", 4, 4, 0))
+        extras["fp32_2048_march_K4_B4_mlups"] = round(m2k, 1)
+        extras["fp32_2048_march_algorithmic_hbm_frac"] = round(m2k * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4)
+        _, m2t, _, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=(4, 16))
+        extras["fp32_2048_tile_K4_R16_mlups"] = round(m2t, 1)
         out["extras"] = extras
     if "batch" in sections:
         log("batch: 64-cavity Ra x Pr sweep vs one by one")

@@ -234,6 +234,29 @@ int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
  * from about 512^2 up, 12 rows below that. */
 int dmrt_set_temporal(dmrt_cavity *h, int steps_per_launch, int tile_rows);
 
+/* K = steps_per_launch steps per launch of dmrt_step with workgroups that
+ * march up the rows (the same time steps, Eqs. 25-45, as dmrt_set_temporal,
+ * with less recomputed halo).  Each workgroup holds K groups of group_rows
+ * wavefronts, group j computing step t + j on rows that trail group j - 1
+ * by group_rows + 1, with the newest group_rows + 2 rows of each
+ * intermediate step in an LDS ring; it owns 64 - 2(K - 1) columns and
+ * chunk_rows rows, so the halo recomputed at the K - 1 rows of each chunk
+ * end replaces the one of each 16-row tile.  The first group gathers the
+ * row of its next iteration from global memory one iteration ahead.
+ * (K, group_rows) in {(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3),
+ * (4, 4)}; chunk_rows >= 1, or 0 to pick the largest chunk that keeps one
+ * launch's workgroups resident on the device at once.  DMRT_BC_CAVITY only
+ * (EINVAL otherwise).  Results are identical to single steps.
+ * dmrt_set_temporal switches the marching off.  EHIP if the device query for
+ * chunk_rows = 0 fails.  On MI355X, K = 4 with 3 rows (FP32) or 4 rows (FP64)
+ * and chunk_rows = 0 is the fastest at 1024^2 and above; below about 512^2
+ * the tile kernel of dmrt_set_temporal is faster. */
+int dmrt_set_temporal_march(dmrt_cavity *h, int steps_per_launch, int group_rows, int chunk_rows);
+
+/* The marching mode of dmrt_set_temporal_march: group_rows (0 when off) and
+ * the rows per workgroup in use (0 when off).  Either pointer may be NULL. */
+int dmrt_get_temporal_march(const dmrt_cavity *h, int *group_rows, int *chunk_rows);
+
 /* Device pointers of the two ping-pong copies and the index (0/1) of the
  * copy holding the current state; for callers that manage memory. */
 int dmrt_buffers(dmrt_cavity *h, void **f, void **g, int *current);

@@ -9,8 +9,10 @@ in a JSON file keyed by (device architecture, precision, member sizes).
 Batch schedule dimensions (dmrt_batch_set_schedule): tile shape, tile
 order, workgroups per launch, and cavity groups sized for the 256 MB
 last-level cache that run several steps before the next group.
-Single-cavity dimensions: steps per launch and tile rows
-(dmrt_set_temporal), tile shape and die-aware tile order (dmrt_set_launch).
+Single-cavity dimensions: steps per launch with the tile kernel and its
+rows (dmrt_set_temporal) or with the row-marching kernel and its wave rows
+per step group (dmrt_set_temporal_march, entries ("march", K, B)), tile
+shape and die-aware tile order (dmrt_set_launch).
 Adjoint: steps per backward launch and tile rows (dmrt_adjoint_set_temporal).
 """
 from __future__ import annotations
@@ -37,7 +39,8 @@ BATCH_DEFAULT = {"temporal": (4, 16), "block": (64, 4), "order": 1, "grid_blocks
                  "group": (0, 64)}
 
 CAVITY_SPACE = {
-    "temporal": [(4, 16), (4, 12), (3, 16), (3, 12), (3, 10), (2, 6), (2, 10), (4, 10), (1, 10)],
+    "temporal": [(4, 16), ("march", 4, 3), ("march", 4, 2), ("march", 4, 4), ("march", 4, 1), (4, 12),
+                 (3, 16), (3, 12), (3, 10), (2, 6), (2, 10), (4, 10), (1, 10)],
     "block": [(256, 1), (128, 2), (64, 4), (512, 1), (128, 1), (64, 1), (256, 2)],
     "xcd_remap": [1, 0],
 }
@@ -248,4 +251,8 @@ GRAPH_STEPS = 60       # steps per captured graph: a multiple of every K in 1..4
 def apply_cavity(cavity, cfg):
     """Applies a single-cavity launch configuration (see CAVITY_SPACE)."""
     cavity.set_launch(cfg["block"][0], cfg["block"][1], cfg["xcd_remap"], GRAPH_STEPS)
-    cavity.set_temporal(cfg["temporal"][0], cfg["temporal"][1])
+    t = cfg["temporal"]
+    if t[0] == "march":
+        cavity.set_temporal_march(int(t[1]), int(t[2]), int(t[3]) if len(t) > 3 else 0)
+    else:
+        cavity.set_temporal(int(t[0]), int(t[1]))

@@ -840,6 +840,209 @@ __global__ void __launch_bounds__(kFootW * R) stepk_all_kernel(StepArgs<real> A,
     stepk_tile<real, R, K, true>(A, lds, tile, slot);
 }
 
+// ---------------------------------------------------------------------------
+// K steps per launch, marching up the rows
+// ---------------------------------------------------------------------------
+// The workgroup is K groups of B wavefronts; the waves of group j compute
+// step t + j.  It owns an x tile of 64 - 2(K - 1) columns (64-wide footprint
+// as above) and a chunk of rows [y0, y1) and sweeps it upwards: at
+// iteration i, wave r of group j computes row a_j + B i + r, with
+// a_1 = y0 - (K - 1) and each group B + 1 rows behind the one before, so
+// that the three rows a node gathers from were produced by the previous
+// group in an earlier iteration.  Group j < K keeps its newest B + 2 rows in
+// an LDS ring that group j + 1 reads; group 1 gathers from global memory and
+// group K stores to it.  Each iteration has a compute stage and a ring-write
+// stage separated by barriers.  The rows computed twice are the K - 1 halo
+// rows at each chunk end instead of at each 16-row tile, and the result
+// equals K single-step launches exactly (same gathers, same arithmetic).
+// Wall temperature of row y, uniform per wave: a scalar load through the
+// constant address space, which does not wait for vector memory operations
+// in flight.
+template <typename real>
+__device__ __forceinline__ real thw_row(const real* thw, int y)
+{
+    typedef const __attribute__((address_space(4))) real creal;
+    return ((creal*)thw)[y];
+}
+
+template <typename real, int B>
+__device__ __forceinline__ void gather_ring(const real* ring, real thw_y, int n, int x, int y, int lx,
+                                            int sm, int s0, int sp, const Coef<real>& c, real (&f)[9],
+                                            real (&g)[5])
+{
+    constexpr int PL = (B + 2) * kFootW;
+    const real* bm = ring + (sm * kFootW + lx);   // row y - 1
+    const real* b0 = ring + (s0 * kFootW + lx);   // row y
+    const real* bp = ring + (sp * kFootW + lx);   // row y + 1
+    f[0] = b0[0];
+    f[1] = b0[1 * PL - 1];
+    f[2] = bm[2 * PL];
+    f[3] = b0[3 * PL + 1];
+    f[4] = bp[4 * PL];
+    f[5] = bm[5 * PL - 1];
+    f[6] = bm[6 * PL + 1];
+    f[7] = bp[7 * PL + 1];
+    f[8] = bp[8 * PL - 1];
+    g[0] = b0[9 * PL];
+    g[1] = b0[10 * PL - 1];
+    g[2] = bm[11 * PL];
+    g[3] = b0[12 * PL + 1];
+    g[4] = bp[13 * PL];
+    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
+    if (!(hxm && hxp && hym && hyp)) {
+        if (!hxm) { f[1] = b0[3 * PL]; g[1] = fmr(c.cabb, thw_y, -b0[12 * PL]); }   // Eq. 45
+        if (!hxp) { f[3] = b0[1 * PL]; g[3] = c.cold - b0[10 * PL]; }
+        if (!hym) { f[2] = b0[4 * PL]; g[2] = b0[13 * PL]; }                           // Eq. 44
+        if (!hyp) { f[4] = b0[2 * PL]; g[4] = b0[11 * PL]; }
+        if (!(hxm && hym)) f[5] = b0[7 * PL];
+        if (!(hxp && hym)) f[6] = b0[8 * PL];
+        if (!(hxp && hyp)) f[7] = b0[5 * PL];
+        if (!(hxm && hyp)) f[8] = b0[6 * PL];
+    }
+}
+
+// The cavity gather split in two for prefetching: the loads alone, with
+// selected addresses but no branches (every address in bounds for x, y in
+// [0, n)), and the isothermal-wall formula of Eq. 45 applied to them where
+// the values are used; together they give exactly gather<real, BC_CAVITY>.
+template <typename real>
+__device__ __forceinline__ void gather_cavity_loads(const real* __restrict__ fi, const real* __restrict__ gi,
+                                                    int n, int pitch, int P, int x, int y, real (&f)[9],
+                                                    real (&g)[5])
+{
+    constexpr unsigned E = sizeof(real);
+    const unsigned kb = unsigned(y * pitch + x) * E, Pb = unsigned(P) * E, rb = unsigned(pitch) * E;
+    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
+    f[0] = ldb(fi, kb);
+    f[1] = ldb(fi, hxm ? kb + Pb - E : kb + 3 * Pb);
+    f[2] = ldb(fi, hym ? kb + 2 * Pb - rb : kb + 4 * Pb);
+    f[3] = ldb(fi, hxp ? kb + 3 * Pb + E : kb + Pb);
+    f[4] = ldb(fi, hyp ? kb + 4 * Pb + rb : kb + 2 * Pb);
+    f[5] = ldb(fi, (hxm && hym) ? kb + 5 * Pb - rb - E : kb + 7 * Pb);
+    f[6] = ldb(fi, (hxp && hym) ? kb + 6 * Pb - rb + E : kb + 8 * Pb);
+    f[7] = ldb(fi, (hxp && hyp) ? kb + 7 * Pb + rb + E : kb + 5 * Pb);
+    f[8] = ldb(fi, (hxm && hyp) ? kb + 8 * Pb + rb - E : kb + 6 * Pb);
+    g[0] = ldb(gi, kb);
+    g[1] = ldb(gi, hxm ? kb + Pb - E : kb + 3 * Pb);
+    g[2] = ldb(gi, hym ? kb + 2 * Pb - rb : kb + 4 * Pb);        // Eq. 44
+    g[3] = ldb(gi, hxp ? kb + 3 * Pb + E : kb + Pb);
+    g[4] = ldb(gi, hyp ? kb + 4 * Pb + rb : kb + 2 * Pb);
+}
+
+template <typename real>
+__device__ __forceinline__ void gather_cavity_walls(real thw_y, int n, int x, const Coef<real>& c, real (&g)[5])
+{
+    if (x == 0) g[1] = fmr(c.cabb, thw_y, -g[1]);                // Eq. 45
+    if (x == n - 1) g[3] = c.cold - g[3];
+}
+
+// Per-wave constants of the row-marching kernel.
+template <typename real>
+struct MarchWave {
+    int j, r, x, lx, aj, aK, lo, hi;
+    bool xact;
+    const real* rin;
+    real* rout;
+};
+
+// One iteration of the row-marching kernel for the calling wave: with PF,
+// group 1 computes the row gathered into (cf, cg) one iteration earlier and
+// gathers the row of its next iteration into (nf, ng) first, so that those
+// global loads stay in flight across this iteration's barriers; without PF
+// it gathers its row now.  The other groups gather from the previous
+// group's ring.
+template <typename real, int K, int B, bool PF, bool FIRST>
+__device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchWave<real>& w, int i,
+                                           real (&cf)[9], real (&cg)[5], real (&nf)[9], real (&ng)[5])
+{
+    constexpr int RS = B + 2, PL = RS * kFootW;
+    const int n = A.n, P = A.plane;
+    const int y = w.aj + B * i + w.r;                 // uniform per wave
+    const int s0 = (y - w.aK) % RS;                   // ring slot of row y (y >= aK)
+    const bool act = w.xact && y >= w.lo && y < w.hi;
+    if constexpr (FIRST) {
+        if constexpr (PF) {
+            // unconditional (clamped) loads: the wait for them is then
+            // placed exactly, one iteration later
+            const int xn = min(max(w.x, 0), n - 1), yn = min(max(y + B, 0), n - 1);
+            gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, P, xn, yn, nf, ng);
+            const real tw = thw_row<real>(A.thw, min(max(y, 0), n - 1));
+            if (act) gather_cavity_walls<real>(tw, n, w.x, A.c, cg);
+        } else if (act) {
+            gather<real, BC_CAVITY>(A.fin, A.gin, A.thw, n, A.pitch, P, w.x, y, A.c, cf, cg);
+        }
+    } else if (act) {
+        const int sm = s0 == 0 ? RS - 1 : s0 - 1, sp = s0 == RS - 1 ? 0 : s0 + 1;
+        gather_ring<real, B>(w.rin, thw_row<real>(A.thw, min(max(y, 0), n - 1)), n, w.x, y, w.lx, sm, s0, sp,
+                             A.c, cf, cg);
+    }
+    if (act) {
+        real th, ux, uy;
+        collide<real>(cf, cg, A.c, th, ux, uy);
+    }
+    __syncthreads();
+    if (act) {
+        if (FIRST || w.j < K) {
+            real* o = w.rout + (s0 * kFootW + w.lx);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) o[q * PL] = cf[q];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) o[(9 + q) * PL] = cg[q];
+        } else {
+            const unsigned kb = unsigned(y * A.pitch + w.x) * sizeof(real), Pb = unsigned(P) * sizeof(real);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) stb(A.fout, kb + q * Pb, cf[q]);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) stb(A.gout, kb + q * Pb, cg[q]);
+        }
+    }
+    __syncthreads();
+}
+
+template <typename real, int K, int B, bool PF>
+__global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A, int chunk)
+{
+    constexpr int RS = B + 2, W = kFootW - 2 * (K - 1), RING = 14 * RS * kFootW;
+    static_assert(K >= 2 && W > 0, "K out of range");
+    __shared__ real lds[(K - 1) * RING];
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;                      // uniform per workgroup
+    const int tyt = tile / A.tiles_x;
+    const int txt = tile - tyt * A.tiles_x;
+    MarchWave<real> w;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);   // blockDim.x = 64: one wave per y index
+    w.j = wv / B + 1;
+    w.r = wv - (w.j - 1) * B;
+    w.lx = threadIdx.x;
+    w.x = txt * W - (K - 1) + w.lx;
+    const int n = A.n;
+    const int y0 = tyt * chunk, y1 = min(y0 + chunk, n);
+    const int a1 = y0 - (K - 1);
+    w.aj = a1 - (w.j - 1) * (B + 1);
+    w.aK = a1 - (K - 1) * (B + 1);
+    const int T = (y1 - 1 - w.aK) / B + 1;            // iterations until group K has passed y1 - 1
+    w.lo = max(y0 - (K - w.j), 0);
+    w.hi = min(y1 + (K - w.j), n);
+    w.xact = w.x >= 0 && w.x < n && w.lx >= w.j - 1 && w.lx <= kFootW - w.j;
+    w.rin = lds + (w.j >= 2 ? (w.j - 2) * RING : 0);
+    w.rout = lds + (w.j < K ? (w.j - 1) * RING : 0);
+    real af[9], ag[5], bf[9], bg[5];
+    if (PF && w.j == 1)
+        gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, A.plane, min(max(w.x, 0), n - 1),
+                                  min(max(w.aj + w.r, 0), n - 1), af, ag);
+    // group 1 and the others run separate loops (the same number of
+    // barriers each); two iterations per trip with the roles of the two
+    // register sets swapped, so the prefetched values need no copies
+    if (w.j == 1) {
+        for (int i = 0; i < T; i += 2) {
+            march_iter<real, K, B, PF, true>(A, w, i, af, ag, bf, bg);
+            if (i + 1 < T) march_iter<real, K, B, PF, true>(A, w, i + 1, bf, bg, af, ag);
+        }
+    } else {
+        for (int i = 0; i < T; ++i) march_iter<real, K, B, PF, false>(A, w, i, af, ag, bf, bg);
+    }
+}
+
 // lambda at footprint node (lx, ly) from mu of the previous phase in LDS:
 // interior links first (one base address, constant offsets), then the wall
 // links of lanes on a wall.

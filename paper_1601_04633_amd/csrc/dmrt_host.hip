@@ -758,6 +758,37 @@ int dmrt_set_temporal(dmrt_cavity* h, int steps_per_launch, int tile_rows)
     if (h->adj) { free_adjoint(h->adj); h->adj = nullptr; }   // its graphs bake the mode
     h->temporal = steps_per_launch;
     h->t_rows = tile_rows;
+    h->march = 0;
+    return DMRT_OK;
+}
+
+int dmrt_set_temporal_march(dmrt_cavity* h, int steps_per_launch, int group_rows, int chunk_rows)
+{
+    if (!h) return DMRT_EINVAL;
+    if (!valid_march(steps_per_launch, group_rows) || chunk_rows < 0) return DMRT_EINVAL;
+    if (h->p.bc_mode != DMRT_BC_CAVITY) return DMRT_EINVAL;
+    DeviceGuard g(h->dev);
+    int chunk = chunk_rows;
+    if (chunk == 0)
+        chunk = h->esz == sizeof(double)
+                    ? march_chunk_auto<double>(h->n, steps_per_launch, group_rows, h->dev)
+                    : march_chunk_auto<float>(h->n, steps_per_launch, group_rows, h->dev);
+    if (chunk <= 0) return DMRT_EHIP;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    if (h->adj) { free_adjoint(h->adj); h->adj = nullptr; }
+    h->temporal = steps_per_launch;
+    if (!valid_temporal(steps_per_launch, h->t_rows)) h->t_rows = 10;   // the Nusselt-window launches
+    h->march = group_rows;
+    h->march_chunk = std::min(chunk, h->n);
+    return DMRT_OK;
+}
+
+int dmrt_get_temporal_march(const dmrt_cavity* h, int* group_rows, int* chunk_rows)
+{
+    if (!h) return DMRT_EINVAL;
+    if (group_rows) *group_rows = h->march;
+    if (chunk_rows) *chunk_rows = h->march ? h->march_chunk : 0;
     return DMRT_OK;
 }
 

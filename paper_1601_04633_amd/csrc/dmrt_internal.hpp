@@ -45,6 +45,7 @@ void free_adjoint(AdjointState* a);
 
 }  // namespace dmrt
 
+#include <algorithm>
 #include <vector>
 
 struct dmrt_cavity {
@@ -78,6 +79,8 @@ struct dmrt_cavity {
     // launch
     int block_x = 256, block_y = 1, xcd_remap = 1, graph_steps = 60;   // 60: a multiple of every K
     int temporal = 1, t_rows = 10;    // steps per launch (1, or 2..4 through LDS) and its tile rows
+    int march = 0, march_chunk = 0;   // K-step launches marching up the rows: wave rows per step
+                                      // group (0: off) and rows per workgroup
     int adj_temporal = 1, adj_rows = 10;   // the same for the adjoint's backward launches
     int graph_flips[2] = {0, 0};      // copy changes made by one replay of graph[p]
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -114,6 +117,72 @@ inline bool valid_temporal(int k, int rows)
     return false;
 }
 
+// The (steps per launch K, wave rows per step group B) pairs of the
+// row-marching K-step kernel (K B wavefronts per workgroup).
+#define DMRT_FOR_EACH_KB(X) X(2, 8) X(3, 2) X(3, 4) X(4, 1) X(4, 2) X(4, 3) X(4, 4)
+#ifndef MARCH_PF
+#define MARCH_PF true
+#endif
+
+inline bool valid_march(int k, int b)
+{
+#define DMRT_KB_OK(KK, BB) if (k == KK && b == BB) return true;
+    DMRT_FOR_EACH_KB(DMRT_KB_OK)
+#undef DMRT_KB_OK
+    return false;
+}
+
+// Rows per workgroup of the row-marching kernel that leave every workgroup
+// of one launch resident at once (at least 1 row).
+template <typename real>
+int march_chunk_auto(int n, int K, int B, int dev)
+{
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return -1;
+#define DMRT_KB_OCC(KK, BB)                                                                      \
+    if (K == KK && B == BB &&                                                                    \
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stepm_kernel<real, KK, BB, MARCH_PF>,       \
+                                                     kFootW * KK * BB, 0) != hipSuccess)          \
+        return -1;
+    DMRT_FOR_EACH_KB(DMRT_KB_OCC)
+#undef DMRT_KB_OCC
+    if (per_cu <= 0) return -1;
+    const int W = kFootW - 2 * (K - 1);
+    const int tiles_x = (n + W - 1) / W;
+    const int chunks = std::max(1, per_cu * cus / tiles_x);
+    return std::max(1, (n + chunks - 1) / chunks);
+}
+
+// Launches K = h->temporal steps of the cavity with the row-marching kernel
+// (h->march wave rows per step group, h->march_chunk rows per workgroup).
+template <typename real>
+int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
+                 real* gout)
+{
+    const int K = h->temporal, B = h->march, chunk = h->march_chunk;
+    StepArgs<real> A;
+    A.fin = fin; A.gin = gin; A.fout = fout; A.gout = gout;
+    A.thw = static_cast<const real*>(h->thw_real);
+    A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
+    const int W = kFootW - 2 * (K - 1);
+    A.tiles_x = (h->n + W - 1) / W;
+    A.tiles = A.tiles_x * ((h->n + chunk - 1) / chunk);
+    A.xcd_remap = h->xcd_remap;
+    A.c = make_coef<real>(h->p, h->d);
+    int nblocks = A.tiles;
+    if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
+    const dim3 grid(nblocks), block(kFootW, K * B);
+#define DMRT_KB(KK, BB)                                                                 \
+    if (K == KK && B == BB) {                                                            \
+        hipLaunchKernelGGL((stepm_kernel<real, KK, BB, MARCH_PF>), grid, block, 0, s, A, chunk);   \
+        return record_hip(hipGetLastError(), "stepm_kernel");                           \
+    }
+    DMRT_FOR_EACH_KB(DMRT_KB)
+#undef DMRT_KB
+    return DMRT_EINVAL;
+}
+
 // Launches K = h->temporal steps of the cavity from (fin, gin) to (fout, gout)
 // through LDS with footprint rows h->t_rows (K >= 2).  With acc non-null the
 // launch also adds each step's hot-wall Nusselt row sums to acc (FP64, n
@@ -122,6 +191,7 @@ template <typename real>
 int launch_stepk(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
                  real* gout, const double* thw_d = nullptr, double* acc = nullptr)
 {
+    if (h->march && !acc) return launch_stepm<real>(h, s, fin, gin, fout, gout);
     const int K = h->temporal, R = h->t_rows;
     StepArgs<real> A;
     A.fin = fin; A.gin = gin; A.fout = fout; A.gout = gout;

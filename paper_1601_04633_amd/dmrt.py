@@ -96,6 +96,8 @@ _SIGS = {
     "dmrt_load_state": [_vp, _vp, _c_size],
     "dmrt_set_launch": [_vp, _c_int, _c_int, _c_int, _c_int],
     "dmrt_set_temporal": [_vp, _c_int, _c_int],
+    "dmrt_set_temporal_march": [_vp, _c_int, _c_int, _c_int],
+    "dmrt_get_temporal_march": [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)],
     "dmrt_buffers": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_c_int)],
     "dmrt_destroy": [_vp],
     "dmrt_adjoint_forward": [_vp, _c_long, _c_long, _c_long, _dp],
@@ -346,6 +348,20 @@ class Cavity:
 
     def set_temporal(self, steps_per_launch=4, tile_rows=16):
         check(dmrt_set_temporal(self._h, steps_per_launch, tile_rows), "dmrt_set_temporal")
+
+    def set_temporal_march(self, steps_per_launch=4, group_rows=4, chunk_rows=0):
+        """K steps per launch with workgroups marching up chunks of rows;
+        returns the rows per workgroup in use."""
+        check(dmrt_set_temporal_march(self._h, steps_per_launch, group_rows, chunk_rows),
+              "dmrt_set_temporal_march")
+        return self.temporal_march()[1]
+
+    def temporal_march(self):
+        """(wave rows per step group, rows per workgroup); (0, 0) when off."""
+        b, c = _c_int(0), _c_int(0)
+        check(dmrt_get_temporal_march(self._h, ctypes.byref(b), ctypes.byref(c)),
+              "dmrt_get_temporal_march")
+        return b.value, c.value
 
     def buffers(self):
         f, g, c = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int(0)

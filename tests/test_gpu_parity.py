@@ -304,6 +304,45 @@ def test_multi_step_launch_equals_single_steps(precision, k, rows):
         np.testing.assert_array_equal(ref.nu_series_read(), two.nu_series_read())
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("k,group", [(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3), (4, 4)])
+def test_marching_launch_equals_single_steps(precision, k, group):
+    """K steps per launch with workgroups marching up chunks of rows give
+    bitwise the state of single steps: ragged sizes, chunks of one row, of a
+    few rows, not dividing n, the whole height and the automatic choice,
+    odd step counts, graph replay and Nu sampling that splits groups."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    for n, chunk in ((4, 0), (5, 1), (37, 5), (63, 0), (100, 7), (130, 37), (257, 0), (70, 70)):
+        print(f"[parity] march K={k} B={group} n={n} chunk={chunk} {precision}", flush=True)
+        th0 = inputs.theta_noise(n, 40 + n, amp=1e-2)
+        ref = Cavity(n=n, Ra=2e4, Pr=0.01, precision=precision)
+        ref.set_theta(th0)
+        ref.nu_series(7, 100)
+        ref.step(131)
+        m = Cavity(n=n, Ra=2e4, Pr=0.01, precision=precision)
+        used = m.set_temporal_march(k, group, chunk)
+        assert (chunk == 0 and 1 <= used <= n) or used == min(chunk, n)
+        assert m.temporal_march() == (group, used)
+        m.set_theta(th0)
+        m.nu_series(7, 100)
+        m.step(67)
+        m.step(64)
+        fa, ga = ref.raw_state()
+        fb, gb = m.raw_state()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), (n, k, group, chunk)
+        np.testing.assert_array_equal(ref.nu_series_read(), m.nu_series_read())
+        ref.close()
+        m.close()
+
+
+def test_marching_fp64_matches_oracle(oracle_mod):
+    o, c = _pair(oracle_mod, 100, 1e4, 0.01)
+    c.set_temporal_march(4, 4, 0)
+    o.step(151)
+    c.step(151)
+    _compare_fields(o, c, 1e-12)
+
+
 @pytest.mark.parametrize("k,rows", [(2, 10), (3, 10), (4, 16)])
 def test_multi_step_fp64_matches_oracle(oracle_mod, k, rows):
     o, c = _pair(oracle_mod, 100, 1e4, 0.01)
@@ -318,6 +357,23 @@ def test_two_step_rejected_outside_cavity():
     c = Cavity(n=32, Ra=1e4, Pr=0.01, bc_mode=1)
     with pytest.raises(DmrtError):
         c.set_temporal(2, 10)
+
+
+def test_marching_rejects_bad_arguments():
+    from paper_1601_04633_amd.dmrt import Cavity, DmrtError
+    c = Cavity(n=32, Ra=1e4, Pr=0.01)
+    for args in ((4, 5, 0), (1, 4, 0), (5, 4, 0), (4, 4, -1), (2, 4, 0)):
+        with pytest.raises(DmrtError):
+            c.set_temporal_march(*args)
+    assert c.temporal_march() == (0, 0)
+    c.set_temporal_march(4, 4, 10)
+    c.set_temporal(4, 16)                      # tile kernel again: marching off
+    assert c.temporal_march() == (0, 0)
+    c.close()
+    p = Cavity(n=32, Ra=1e4, Pr=0.01, bc_mode=1)
+    with pytest.raises(DmrtError):
+        p.set_temporal_march(4, 4, 0)
+    p.close()
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
