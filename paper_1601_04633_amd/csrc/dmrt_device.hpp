@@ -851,10 +851,12 @@ __global__ void __launch_bounds__(kFootW * R) stepk_all_kernel(StepArgs<real> A,
 // that the three rows a node gathers from were produced by the previous
 // group in an earlier iteration.  Group j < K keeps its newest B + 2 rows in
 // an LDS ring that group j + 1 reads; group 1 gathers from global memory and
-// group K stores to it.  Each iteration has a compute stage and a ring-write
-// stage separated by barriers.  The rows computed twice are the K - 1 halo
-// rows at each chunk end instead of at each 16-row tile, and the result
-// equals K single-step launches exactly (same gathers, same arithmetic).
+// group K stores to it.  Odd chunks run the same schedule downwards.  Each
+// iteration has a compute stage and a ring-write stage separated by
+// barriers.  The rows computed twice are the K - 1 halo rows at each chunk
+// end instead of at each 16-row tile, and the result equals K single-step
+// launches exactly (same gathers, same arithmetic).
+
 // Wall temperature of row y, uniform per wave: a scalar load through the
 // constant address space, which does not wait for vector memory operations
 // in flight.
@@ -939,8 +941,8 @@ __device__ __forceinline__ void gather_cavity_walls(real thw_y, int n, int x, co
 // Per-wave constants of the row-marching kernel.
 template <typename real>
 struct MarchWave {
-    int j, r, x, lx, aj, aK, lo, hi;
-    bool xact;
+    int j, r, x, lx, aj, aK, lo, hi, ymir;
+    bool xact, down;
     const real* rin;
     real* rout;
 };
@@ -957,14 +959,16 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
 {
     constexpr int RS = B + 2, PL = RS * kFootW;
     const int n = A.n, P = A.plane;
-    const int y = w.aj + B * i + w.r;                 // uniform per wave
-    const int s0 = (y - w.aK) % RS;                   // ring slot of row y (y >= aK)
-    const bool act = w.xact && y >= w.lo && y < w.hi;
+    const int v = w.aj + B * i + w.r;                 // marching row, uniform per wave
+    const int y = w.down ? w.ymir - v : v;            // the cavity row it stands for
+    const int s0 = (v - w.aK) % RS;                   // ring slot of row v (v >= aK)
+    const bool act = w.xact && v >= w.lo && v < w.hi && y >= 0 && y < n;
     if constexpr (FIRST) {
         if constexpr (PF) {
             // unconditional (clamped) loads: the wait for them is then
             // placed exactly, one iteration later
-            const int xn = min(max(w.x, 0), n - 1), yn = min(max(y + B, 0), n - 1);
+            const int xn = min(max(w.x, 0), n - 1);
+            const int yn = min(max(w.down ? w.ymir - v - B : v + B, 0), n - 1);
             gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, P, xn, yn, nf, ng);
             const real tw = thw_row<real>(A.thw, min(max(y, 0), n - 1));
             if (act) gather_cavity_walls<real>(tw, n, w.x, A.c, cg);
@@ -972,9 +976,11 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
             gather<real, BC_CAVITY>(A.fin, A.gin, A.thw, n, A.pitch, P, w.x, y, A.c, cf, cg);
         }
     } else if (act) {
+        // slots of rows v - 1 and v + 1: rows y - 1 and y + 1 when marching
+        // up, y + 1 and y - 1 when marching down
         const int sm = s0 == 0 ? RS - 1 : s0 - 1, sp = s0 == RS - 1 ? 0 : s0 + 1;
-        gather_ring<real, B>(w.rin, thw_row<real>(A.thw, min(max(y, 0), n - 1)), n, w.x, y, w.lx, sm, s0, sp,
-                             A.c, cf, cg);
+        gather_ring<real, B>(w.rin, thw_row<real>(A.thw, min(max(y, 0), n - 1)), n, w.x, y, w.lx,
+                             w.down ? sp : sm, s0, w.down ? sm : sp, A.c, cf, cg);
     }
     if (act) {
         real th, ux, uy;
@@ -1021,15 +1027,20 @@ __global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A,
     w.aj = a1 - (w.j - 1) * (B + 1);
     w.aK = a1 - (K - 1) * (B + 1);
     const int T = (y1 - 1 - w.aK) / B + 1;            // iterations until group K has passed y1 - 1
-    w.lo = max(y0 - (K - w.j), 0);
-    w.hi = min(y1 + (K - w.j), n);
+    w.lo = y0 - (K - w.j);
+    w.hi = y1 + (K - w.j);
+    // odd chunks march down (row y0 + y1 - 1 - v for marching row v), so
+    // that two neighbouring chunks read the rows they share at the same
+    // time, at the end of both sweeps or at the start of both
+    w.down = (tyt & 1) != 0;
+    w.ymir = y0 + y1 - 1;
     w.xact = w.x >= 0 && w.x < n && w.lx >= w.j - 1 && w.lx <= kFootW - w.j;
     w.rin = lds + (w.j >= 2 ? (w.j - 2) * RING : 0);
     w.rout = lds + (w.j < K ? (w.j - 1) * RING : 0);
     real af[9], ag[5], bf[9], bg[5];
     if (PF && w.j == 1)
         gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, A.plane, min(max(w.x, 0), n - 1),
-                                  min(max(w.aj + w.r, 0), n - 1), af, ag);
+                                  min(max(w.down ? w.ymir - w.aj - w.r : w.aj + w.r, 0), n - 1), af, ag);
     // group 1 and the others run separate loops (the same number of
     // barriers each); two iterations per trip with the roles of the two
     // register sets swapped, so the prefetched values need no copies
