@@ -162,20 +162,24 @@ def test_autograd_function():
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_multi_step_forward_does_not_change_gradients(precision):
-    """The checkpointed forward may take K steps per launch, also inside the
-    objective window, where the K-step launches accumulate the Nusselt sums
-    themselves; J and the gradients are bitwise those of single-step
-    launches, with a window length that is not a multiple of K and a cavity
-    wider than one tile."""
+    """The checkpointed forward may take K steps per launch (tile or
+    row-marching kernel), also inside the objective window, where the
+    K-step launches accumulate the Nusselt sums themselves; J and the
+    gradients are bitwise those of single-step launches, with a window
+    length that is not a multiple of K and a cavity wider than one tile."""
     from paper_1601_04633_amd.dmrt import Cavity
     n, N, K, C = 70, 401, 149, 64
     tw = inputs.hot_wall_profile(n, 29)
     t0 = inputs.theta_noise(n, 30, amp=1e-2)
     out = []
-    for temporal in ((1, 10), (2, 6), (2, 16), (3, 10), (3, 12), (4, 12), (4, 16)):
+    for temporal in ((1, 10), (2, 6), (2, 16), (3, 10), (3, 12), (4, 12), (4, 16), ("march", 4, 3),
+                     ("march", 3, 2, 9)):
         print(f"[adjoint] forward steps/launch, rows {temporal} {precision}", flush=True)
         c = Cavity(n=n, Ra=1e4, Pr=0.01, precision=precision)
-        c.set_temporal(*temporal)
+        if temporal[0] == "march":
+            c.set_temporal_march(*temporal[1:])
+        else:
+            c.set_temporal(*temporal)
         c.set_hot_wall(tw)
         c.set_theta(t0)
         out.append(c.adjoint_nu(N, K, C))
