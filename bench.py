@@ -35,8 +35,8 @@ TRAFFIC_FILES = {
     "step_kernel<float, 0>": os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json"),
     "stepk_kernel<float, 16, 4>": os.path.join(ROOT, "profiles",
                                                "stepk_kernel_K4_R16_cavity_1024_fp32_traffic.json"),
-    "stepm_kernel<float, 4, 3, true>": os.path.join(ROOT, "profiles",
-                                                    "stepm_kernel_K4_B3_cavity_1024_fp32_traffic.json"),
+    "stepm_kernel<float, 4, 3>": os.path.join(ROOT, "profiles",
+                                              "stepm_kernel_K4_B3_cavity_1024_fp32_traffic.json"),
 }
 # launch configuration timed by default (the fastest for this workload on
 # MI355X): four steps per launch through LDS, 64 x 16 footprints,
@@ -102,7 +102,7 @@ def steps_per_launch(temporal):
 def kernel_name(temporal, esz):
     t = "float" if esz == 4 else "double"
     if temporal[0] == "march":
-        return f"stepm_kernel<{t}, {temporal[1]}, {temporal[2]}, true>"
+        return f"stepm_kernel<{t}, {temporal[1]}, {temporal[2]}>"
     if temporal[0] >= 2:
         return f"stepk_kernel<{t}, {temporal[1]}, {temporal[0]}>"
     return f"step_kernel<{t}, 0>"
@@ -432,8 +432,8 @@ def main():
         extras["fp32_single_step_mlups"] = round(m1, 1)
         extras["fp32_single_step_hbm_frac"] = round(m1 * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4)
         log("extra: 2048^2 fp32 control (state larger than the 256 MB last-level cache)")
-        _, m2k, _, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=("march", 4, 4, 0))
-        extras["fp32_2048_march_K4_B4_mlups"] = round(m2k, 1)
+        _, m2k, _, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=("march", 6, 2, 0))
+        extras["fp32_2048_march_K6_B2_mlups"] = round(m2k, 1)
         extras["fp32_2048_march_algorithmic_hbm_frac"] = round(m2k * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4)
         _, m2t, _, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=(4, 16))
         extras["fp32_2048_tile_K4_R16_mlups"] = round(m2t, 1)

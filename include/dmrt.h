@@ -244,13 +244,16 @@ int dmrt_set_temporal(dmrt_cavity *h, int steps_per_launch, int tile_rows);
  * end replaces the one of each 16-row tile.  The first group gathers the
  * row of its next iteration from global memory one iteration ahead.
  * (K, group_rows) in {(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3),
- * (4, 4)}; chunk_rows >= 1, or 0 to pick the largest chunk that keeps one
+ * (4, 4), (6, 2)} (the LDS rings, (K - 1) x 14 x (group_rows + 2) x 64
+ * elements, fit 160 KB in both precisions); chunk_rows >= 1, or 0 to pick the largest chunk that keeps one
  * launch's workgroups resident on the device at once.  DMRT_BC_CAVITY only
  * (EINVAL otherwise).  Results are identical to single steps.
  * dmrt_set_temporal switches the marching off.  EHIP if the device query for
- * chunk_rows = 0 fails.  On MI355X, K = 4 with 3 rows (FP32) or 4 rows (FP64)
- * and chunk_rows = 0 is the fastest at 1024^2 and above; below about 512^2
- * the tile kernel of dmrt_set_temporal is faster. */
+ * chunk_rows = 0 fails.  On MI355X with chunk_rows = 0: K = 4 with 3 rows
+ * (FP32) or 4 rows (FP64) is the fastest at 1024^2, K = 6 with 2 rows at
+ * 2048^2 (where the state no longer fits the last-level cache and fewer
+ * launches per step pay); below about 512^2 the tile kernel of
+ * dmrt_set_temporal is faster. */
 int dmrt_set_temporal_march(dmrt_cavity *h, int steps_per_launch, int group_rows, int chunk_rows);
 
 /* The marching mode of dmrt_set_temporal_march: group_rows (0 when off) and

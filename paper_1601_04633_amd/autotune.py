@@ -39,7 +39,7 @@ BATCH_DEFAULT = {"temporal": (4, 16), "block": (64, 4), "order": 1, "grid_blocks
                  "group": (0, 64)}
 
 CAVITY_SPACE = {
-    "temporal": [(4, 16), ("march", 4, 3), ("march", 4, 2), ("march", 4, 4), ("march", 4, 1), (4, 12),
+    "temporal": [(4, 16), ("march", 4, 3), ("march", 4, 2), ("march", 4, 4), ("march", 6, 2), ("march", 4, 1), (4, 12),
                  (3, 16), (3, 12), (3, 10), (2, 6), (2, 10), (4, 10), (1, 10)],
     "block": [(256, 1), (128, 2), (64, 4), (512, 1), (128, 1), (64, 1), (256, 2)],
     "xcd_remap": [1, 0],
@@ -245,7 +245,7 @@ def tune_adjoint(cavity, nsteps=2000, avg_last=400, ckpt_every=500, stream_ptr=N
     return best, best_t, trials
 
 
-GRAPH_STEPS = 60       # steps per captured graph: a multiple of every K in 1..4
+GRAPH_STEPS = 60       # steps per captured graph: a multiple of every K offered (1..4, 6)
 
 
 def apply_cavity(cavity, cfg):

@@ -133,9 +133,11 @@ int enqueue_fwd(dmrt_cavity* h, AdjointState* a, hipStream_t s, int from, long c
 {
     int c = from, nf = 0;
     long i = 0;
+    // the Nusselt-accumulating K-step launches exist in the tile form only
+    const bool kstep = h->temporal >= 2 && (!nu || valid_temporal(h->temporal, h->t_rows));
     while (i < count) {
         int rc;
-        if (h->temporal >= 2 && i + h->temporal <= count) {
+        if (kstep && i + h->temporal <= count) {
             rc = launch_stepk<real>(h, s, cur_f<real>(h, c), cur_g<real>(h, c), cur_f<real>(h, c ^ 1),
                                     cur_g<real>(h, c ^ 1), nu ? h->thw_dbl : nullptr,
                                     nu ? a->nu_acc : nullptr);

@@ -947,13 +947,12 @@ struct MarchWave {
     real* rout;
 };
 
-// One iteration of the row-marching kernel for the calling wave: with PF,
-// group 1 computes the row gathered into (cf, cg) one iteration earlier and
-// gathers the row of its next iteration into (nf, ng) first, so that those
-// global loads stay in flight across this iteration's barriers; without PF
-// it gathers its row now.  The other groups gather from the previous
-// group's ring.
-template <typename real, int K, int B, bool PF, bool FIRST>
+// One iteration of the row-marching kernel for the calling wave: group 1
+// computes the row gathered into (cf, cg) one iteration earlier and gathers
+// the row of its next iteration into (nf, ng) first, so that those global
+// loads stay in flight across this iteration's barriers.  The other groups
+// gather from the previous group's ring.
+template <typename real, int K, int B, bool FIRST>
 __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchWave<real>& w, int i,
                                            real (&cf)[9], real (&cg)[5], real (&nf)[9], real (&ng)[5])
 {
@@ -964,17 +963,13 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
     const int s0 = (v - w.aK) % RS;                   // ring slot of row v (v >= aK)
     const bool act = w.xact && v >= w.lo && v < w.hi && y >= 0 && y < n;
     if constexpr (FIRST) {
-        if constexpr (PF) {
-            // unconditional (clamped) loads: the wait for them is then
-            // placed exactly, one iteration later
-            const int xn = min(max(w.x, 0), n - 1);
-            const int yn = min(max(w.down ? w.ymir - v - B : v + B, 0), n - 1);
-            gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, P, xn, yn, nf, ng);
-            const real tw = thw_row<real>(A.thw, min(max(y, 0), n - 1));
-            if (act) gather_cavity_walls<real>(tw, n, w.x, A.c, cg);
-        } else if (act) {
-            gather<real, BC_CAVITY>(A.fin, A.gin, A.thw, n, A.pitch, P, w.x, y, A.c, cf, cg);
-        }
+        // unconditional (clamped) loads: the wait for them is then placed
+        // exactly, one iteration later
+        const int xn = min(max(w.x, 0), n - 1);
+        const int yn = min(max(w.down ? w.ymir - v - B : v + B, 0), n - 1);
+        gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, P, xn, yn, nf, ng);
+        const real tw = thw_row<real>(A.thw, min(max(y, 0), n - 1));
+        if (act) gather_cavity_walls<real>(tw, n, w.x, A.c, cg);
     } else if (act) {
         // slots of rows v - 1 and v + 1: rows y - 1 and y + 1 when marching
         // up, y + 1 and y - 1 when marching down
@@ -1005,7 +1000,7 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
     __syncthreads();
 }
 
-template <typename real, int K, int B, bool PF>
+template <typename real, int K, int B>
 __global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A, int chunk)
 {
     constexpr int RS = B + 2, W = kFootW - 2 * (K - 1), RING = 14 * RS * kFootW;
@@ -1038,7 +1033,7 @@ __global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A,
     w.rin = lds + (w.j >= 2 ? (w.j - 2) * RING : 0);
     w.rout = lds + (w.j < K ? (w.j - 1) * RING : 0);
     real af[9], ag[5], bf[9], bg[5];
-    if (PF && w.j == 1)
+    if (w.j == 1)
         gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, A.plane, min(max(w.x, 0), n - 1),
                                   min(max(w.down ? w.ymir - w.aj - w.r : w.aj + w.r, 0), n - 1), af, ag);
     // group 1 and the others run separate loops (the same number of
@@ -1046,11 +1041,11 @@ __global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A,
     // register sets swapped, so the prefetched values need no copies
     if (w.j == 1) {
         for (int i = 0; i < T; i += 2) {
-            march_iter<real, K, B, PF, true>(A, w, i, af, ag, bf, bg);
-            if (i + 1 < T) march_iter<real, K, B, PF, true>(A, w, i + 1, bf, bg, af, ag);
+            march_iter<real, K, B, true>(A, w, i, af, ag, bf, bg);
+            if (i + 1 < T) march_iter<real, K, B, true>(A, w, i + 1, bf, bg, af, ag);
         }
     } else {
-        for (int i = 0; i < T; ++i) march_iter<real, K, B, PF, false>(A, w, i, af, ag, bf, bg);
+        for (int i = 0; i < T; ++i) march_iter<real, K, B, false>(A, w, i, af, ag, bf, bg);
     }
 }
 

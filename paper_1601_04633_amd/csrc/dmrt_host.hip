@@ -765,7 +765,7 @@ int dmrt_set_temporal(dmrt_cavity* h, int steps_per_launch, int tile_rows)
 int dmrt_set_temporal_march(dmrt_cavity* h, int steps_per_launch, int group_rows, int chunk_rows)
 {
     if (!h) return DMRT_EINVAL;
-    if (!valid_march(steps_per_launch, group_rows) || chunk_rows < 0) return DMRT_EINVAL;
+    if (!valid_march(steps_per_launch, group_rows, int(h->esz)) || chunk_rows < 0) return DMRT_EINVAL;
     if (h->p.bc_mode != DMRT_BC_CAVITY) return DMRT_EINVAL;
     DeviceGuard g(h->dev);
     int chunk = chunk_rows;
@@ -778,7 +778,9 @@ int dmrt_set_temporal_march(dmrt_cavity* h, int steps_per_launch, int group_rows
     drop_graphs(h);
     if (h->adj) { free_adjoint(h->adj); h->adj = nullptr; }
     h->temporal = steps_per_launch;
-    if (!valid_temporal(steps_per_launch, h->t_rows)) h->t_rows = 10;   // the Nusselt-window launches
+    // the adjoint's Nusselt-window launches use the tile form: keep its rows
+    // valid for this K where the tile form has K (else those run single steps)
+    if (steps_per_launch <= 4 && !valid_temporal(steps_per_launch, h->t_rows)) h->t_rows = 10;
     h->march = group_rows;
     h->march_chunk = std::min(chunk, h->n);
     return DMRT_OK;

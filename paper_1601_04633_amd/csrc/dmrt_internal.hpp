@@ -118,15 +118,20 @@ inline bool valid_temporal(int k, int rows)
 }
 
 // The (steps per launch K, wave rows per step group B) pairs of the
-// row-marching K-step kernel (K B wavefronts per workgroup).
-#define DMRT_FOR_EACH_KB(X) X(2, 8) X(3, 2) X(3, 4) X(4, 1) X(4, 2) X(4, 3) X(4, 4)
-#ifndef MARCH_PF
-#define MARCH_PF true
-#endif
+// row-marching K-step kernel (K B wavefronts per workgroup); a pair exists
+// for a precision when its LDS rings fit a workgroup's 160 KB.
+#define DMRT_FOR_EACH_KB(X) X(2, 8) X(3, 2) X(3, 4) X(4, 1) X(4, 2) X(4, 3) X(4, 4) X(6, 2)
 
-inline bool valid_march(int k, int b)
+constexpr long kLdsBytes = 160 * 1024;
+
+constexpr long march_lds_bytes(int k, int b, int esz)
 {
-#define DMRT_KB_OK(KK, BB) if (k == KK && b == BB) return true;
+    return long(k - 1) * 14 * (b + 2) * kFootW * esz;
+}
+
+inline bool valid_march(int k, int b, int esz)
+{
+#define DMRT_KB_OK(KK, BB) if (k == KK && b == BB) return march_lds_bytes(k, b, esz) <= kLdsBytes;
     DMRT_FOR_EACH_KB(DMRT_KB_OK)
 #undef DMRT_KB_OK
     return false;
@@ -141,10 +146,11 @@ int march_chunk_auto(int n, int K, int B, int dev)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         return -1;
 #define DMRT_KB_OCC(KK, BB)                                                                      \
-    if (K == KK && B == BB &&                                                                    \
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stepm_kernel<real, KK, BB, MARCH_PF>,       \
-                                                     kFootW * KK * BB, 0) != hipSuccess)          \
-        return -1;
+    if constexpr (march_lds_bytes(KK, BB, sizeof(real)) <= kLdsBytes)                             \
+        if (K == KK && B == BB &&                                                                \
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stepm_kernel<real, KK, BB>,     \
+                                                         kFootW * KK * BB, 0) != hipSuccess)      \
+            return -1;
     DMRT_FOR_EACH_KB(DMRT_KB_OCC)
 #undef DMRT_KB_OCC
     if (per_cu <= 0) return -1;
@@ -173,11 +179,12 @@ int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
     int nblocks = A.tiles;
     if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
     const dim3 grid(nblocks), block(kFootW, K * B);
-#define DMRT_KB(KK, BB)                                                                 \
-    if (K == KK && B == BB) {                                                            \
-        hipLaunchKernelGGL((stepm_kernel<real, KK, BB, MARCH_PF>), grid, block, 0, s, A, chunk);   \
-        return record_hip(hipGetLastError(), "stepm_kernel");                           \
-    }
+#define DMRT_KB(KK, BB)                                                                  \
+    if constexpr (march_lds_bytes(KK, BB, sizeof(real)) <= kLdsBytes)                     \
+        if (K == KK && B == BB) {                                                         \
+            hipLaunchKernelGGL((stepm_kernel<real, KK, BB>), grid, block, 0, s, A, chunk);  \
+            return record_hip(hipGetLastError(), "stepm_kernel");                        \
+        }
     DMRT_FOR_EACH_KB(DMRT_KB)
 #undef DMRT_KB
     return DMRT_EINVAL;

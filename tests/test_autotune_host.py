@@ -77,7 +77,7 @@ def test_apply_functions_call_the_setters():
     c = _FakeCavity()
     autotune.apply_cavity(c, {"temporal": (4, 12), "block": (128, 2), "xcd_remap": 0})
     assert ("launch", (128, 2, 0, 60)) in c.calls and ("temporal", (4, 12)) in c.calls
-    assert all(autotune.GRAPH_STEPS % k == 0 for k in (1, 2, 3, 4))
+    assert all(autotune.GRAPH_STEPS % k == 0 for k in (1, 2, 3, 4, 6))
     m = _FakeCavity()
     autotune.apply_cavity(m, {"temporal": ("march", 4, 3), "block": (256, 1), "xcd_remap": 1})
     assert ("march", (4, 3, 0)) in m.calls and not any(k == "temporal" for k, _ in m.calls)
@@ -97,7 +97,7 @@ def test_search_spaces_only_hold_supported_pairs():
     accepts (the header's list for dmrt_set_temporal)."""
     ok = {(1, 4), (1, 6), (1, 10), (1, 16), (2, 4), (2, 6), (2, 10), (2, 16), (3, 6), (3, 10), (3, 12),
           (3, 14), (3, 16), (4, 10), (4, 12), (4, 14), (4, 16)}
-    march_ok = {(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3), (4, 4)}   # dmrt_set_temporal_march
+    march_ok = {(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3), (4, 4), (6, 2)}   # dmrt_set_temporal_march
     for kr in autotune.BATCH_SPACE["temporal"] + autotune.ADJOINT_SPACE:
         assert tuple(kr) in ok, kr
     for kr in autotune.CAVITY_SPACE["temporal"]:

@@ -173,7 +173,7 @@ def test_multi_step_forward_does_not_change_gradients(precision):
     t0 = inputs.theta_noise(n, 30, amp=1e-2)
     out = []
     for temporal in ((1, 10), (2, 6), (2, 16), (3, 10), (3, 12), (4, 12), (4, 16), ("march", 4, 3),
-                     ("march", 3, 2, 9)):
+                     ("march", 3, 2, 9), ("march", 6, 2)):
         print(f"[adjoint] forward steps/launch, rows {temporal} {precision}", flush=True)
         c = Cavity(n=n, Ra=1e4, Pr=0.01, precision=precision)
         if temporal[0] == "march":

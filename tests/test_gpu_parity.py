@@ -305,13 +305,22 @@ def test_multi_step_launch_equals_single_steps(precision, k, rows):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("k,group", [(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3), (4, 4)])
+@pytest.mark.parametrize("k,group", [(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3), (4, 4), (6, 2)])
 def test_marching_launch_equals_single_steps(precision, k, group):
     """K steps per launch with workgroups marching up chunks of rows give
     bitwise the state of single steps: ragged sizes, chunks of one row, of a
     few rows, not dividing n, the whole height and the automatic choice,
-    odd step counts, graph replay and Nu sampling that splits groups."""
-    from paper_1601_04633_amd.dmrt import Cavity
+    odd step counts, graph replay and Nu sampling that splits groups.  A
+    pair whose LDS rings exceed a workgroup's 160 KB in this precision is
+    rejected."""
+    from paper_1601_04633_amd.dmrt import Cavity, DmrtError
+    esz = 8 if precision == "fp64" else 4
+    if (k - 1) * 14 * (group + 2) * 64 * esz > 160 * 1024:
+        c = Cavity(n=32, Ra=2e4, Pr=0.01, precision=precision)
+        with pytest.raises(DmrtError):
+            c.set_temporal_march(k, group, 0)
+        c.close()
+        return
     for n, chunk in ((4, 0), (5, 1), (37, 5), (63, 0), (100, 7), (130, 37), (257, 0), (70, 70)):
         print(f"[parity] march K={k} B={group} n={n} chunk={chunk} {precision}", flush=True)
         th0 = inputs.theta_noise(n, 40 + n, amp=1e-2)
@@ -362,7 +371,7 @@ def test_two_step_rejected_outside_cavity():
 def test_marching_rejects_bad_arguments():
     from paper_1601_04633_amd.dmrt import Cavity, DmrtError
     c = Cavity(n=32, Ra=1e4, Pr=0.01)
-    for args in ((4, 5, 0), (1, 4, 0), (5, 4, 0), (4, 4, -1), (2, 4, 0)):
+    for args in ((4, 5, 0), (1, 4, 0), (5, 2, 0), (8, 2, 0), (4, 4, -1), (2, 4, 0)):
         with pytest.raises(DmrtError):
             c.set_temporal_march(*args)
     assert c.temporal_march() == (0, 0)

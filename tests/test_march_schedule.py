@@ -14,7 +14,7 @@ iteration, not yet overwritten), every cavity row is stored exactly once
 by group K, slots are in range."""
 import pytest
 
-PAIRS = [(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3), (4, 4)]
+PAIRS = [(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3), (4, 4), (6, 2)]
 
 def run_schedule(n, K, B, chunk):
     RS = B + 2
