@@ -231,7 +231,8 @@ int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
  * DMRT_BC_CAVITY only (EINVAL otherwise).  Results are identical to
  * single steps; Nusselt samples are still taken after every stride-th step.
  * Default at creation: K = 1.  On MI355X K = 4 with 16 rows is the fastest
- * from about 512^2 up, 12 rows below that. */
+ * tile shape from about 512^2 up, 12 rows below that; from 1024^2 up the
+ * marching form (dmrt_set_temporal_march) is faster. */
 int dmrt_set_temporal(dmrt_cavity *h, int steps_per_launch, int tile_rows);
 
 /* K = steps_per_launch steps per launch of dmrt_step with workgroups that

@@ -867,6 +867,10 @@ __device__ __forceinline__ real thw_row(const real* thw, int y)
     return ((creal*)thw)[y];
 }
 
+// Gather of node (x, y) at lane lx from the previous group's ring (14
+// planes of B + 2 rows of 64) with the cavity's wall rules, rows y - 1, y
+// and y + 1 being at slots sm, s0 and sp: every interior link from constant
+// offsets, then the wall links of lanes on a wall (as gather_lds).
 template <typename real, int B>
 __device__ __forceinline__ void gather_ring(const real* ring, real thw_y, int n, int x, int y, int lx,
                                             int sm, int s0, int sp, const Coef<real>& c, real (&f)[9],
