@@ -125,14 +125,26 @@ def test_config0_fp64_20000_steps(oracle_mod):
     assert abs(nc - no) <= 1e-12 * no, (nc, no, errs)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_full_size_1024_matches_oracle(oracle_mod, precision, tol):
-    """1024^2, Ra 1e5, Pr 0.001 in the benchmark's launch shape: every field
-    after a few steps (the oracle advances 1M nodes per step slowly)."""
-    print(f"[parity] 1024^2 {precision}", flush=True)
-    o, c = _pair(oracle_mod, 1024, 1e5, 0.001, precision=precision)
+def _set_mode(c, mode):
+    """The benchmark's launch shape (four steps per launch, workgroups of
+    4 x 3 wavefronts marching up chunks of rows) or the tile form (64 x 16
+    footprints); die-aware order and graphs of 60 steps in both."""
     c.set_launch(256, 1, 1, 60)
-    c.set_temporal(4, 16)
+    if mode == "march":
+        c.set_temporal_march(4, 3, 0)
+    else:
+        c.set_temporal(4, 16)
+
+
+@pytest.mark.parametrize("mode", ["march", "tile"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_full_size_1024_matches_oracle(oracle_mod, precision, tol, mode):
+    """1024^2, Ra 1e5, Pr 0.001 in the benchmark's launch shape (and the
+    tile form): every field after a few steps (the oracle advances 1M nodes
+    per step slowly)."""
+    print(f"[parity] 1024^2 {precision} {mode}", flush=True)
+    o, c = _pair(oracle_mod, 1024, 1e5, 0.001, precision=precision)
+    _set_mode(c, mode)
     o.step(8)
     c.step(8)
     _compare_fields(o, c, tol, names=("theta",) if precision == "fp32" else ("U", "V", "theta", "P"))
@@ -385,20 +397,19 @@ def test_marching_rejects_bad_arguments():
     p.close()
 
 
+@pytest.mark.parametrize("mode", ["march", "tile"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_full_size_centro_symmetry_in_benchmark_shape(precision):
-    """1024^2, Ra 1e5, Pr 0.001 in the benchmark's launch shape (four steps
-    per launch, 64 x 16 footprints, die-aware order, graphs of 60 steps),
-    4,000 steps from theta = 0: rotating the cavity by 180 degrees and
-    flipping theta maps the problem onto itself, so theta, U, V stay
-    antisymmetric and P symmetric at full size (a property that holds at
-    any size, where the oracle cannot follow)."""
+def test_full_size_centro_symmetry_in_benchmark_shape(precision, mode):
+    """1024^2, Ra 1e5, Pr 0.001 in the benchmark's launch shape (and the
+    tile form), 4,000 steps from theta = 0: rotating the cavity by 180
+    degrees and flipping theta maps the problem onto itself, so theta, U, V
+    stay antisymmetric and P symmetric at full size (a property that holds
+    at any size, where the oracle cannot follow)."""
     from paper_1601_04633_amd.dmrt import Cavity
-    print(f"[parity] 1024^2 centro-symmetry {precision}", flush=True)
+    print(f"[parity] 1024^2 centro-symmetry {precision} {mode}", flush=True)
     n = 1024
     c = Cavity(n=n, Ra=1e5, Pr=0.001, precision=precision)
-    c.set_launch(256, 1, 1, 60)
-    c.set_temporal(4, 16)
+    _set_mode(c, mode)
     c.set_theta(np.zeros((n, n)))
     c.step(4000)
     U, V, T, P = c.fields()
