@@ -34,19 +34,29 @@ def test_largest_accepted_cavity(precision, n):
     from paper_1601_04633_amd.dmrt import Cavity
     print(f"[edges] largest cavity {n}^2 {precision}", flush=True)
     th0 = inputs.theta_noise(n, 11)
-    out = []
-    for temporal in ((4, 16), (1, 10)):
+    ref = None
+    # single steps first, then the tile form and the row-marching forms
+    # (four steps per launch, and six, whose 8 steps end in two single ones)
+    for temporal in ((1, 10), (4, 16), ("march", 4, 3 if precision == "fp32" else 4), ("march", 6, 2)):
+        print(f"[edges] {n}^2 {precision} {temporal}", flush=True)
         c = Cavity(n=n, Ra=1e5, Pr=0.001, precision=precision)
-        c.set_temporal(*temporal)
+        if temporal[0] == "march":
+            c.set_temporal_march(temporal[1], temporal[2], 0)
+        else:
+            c.set_temporal(*temporal)
         c.set_theta(th0)
         c.step(8)
         U, V, T, P = c.fields()
-        out.append((U, V, T, P, c.nusselt(0)[0]))
+        nu = c.nusselt(0)[0]
         c.close()
-    (U4, V4, T4, P4, nu4), (U1, V1, T1, P1, nu1) = out
-    for a, b in ((U4, U1), (V4, V1), (T4, T1), (P4, P1)):
-        assert np.array_equal(a, b)
-    assert nu4 == nu1
+        if ref is None:
+            ref = (U, V, T, P, nu)
+            continue
+        for a, b in zip((U, V, T, P), ref[:4]):
+            assert np.array_equal(a, b), temporal
+        assert nu == ref[4]
+        del U, V, T, P
+    U4, V4, T4, P4, _ = ref
     assert np.isfinite(T4).all() and np.isfinite(U4).all()
     # P = drho/3: the cavity conserves mass (bounce-back, force image with no
     # density moment), so the total stays at its initial value 0
