@@ -385,7 +385,12 @@ def main():
                      "hbm_minimum_bytes_per_launch": min_bytes,
                      "hbm_minimum_GBs": round(min_gbs, 1),
                      "hbm_minimum_frac": round(min_gbs / HBM_PEAK_GBS, 4),
-                     "valu_busy_frac_counters": None if counters is None else counters.get("valu_busy_frac")},
+                     "valu_busy_frac_counters": None if counters is None else counters.get("valu_busy_frac"),
+                     # VALU issue ceiling without packed FP32: one wave64
+                     # instruction per 4 cycles on each of 1,024 SIMDs at 2.4 GHz
+                     "valu_instructions_per_launch_counters":
+                         None if counters is None else counters.get("valu_instructions_per_launch"),
+                     "valu_peak_wave_instructions_per_s": 1024 * 2.4e9 / 4},
         "launch": {"block": list(launch[:2]), "xcd_remap": launch[2], "graph_steps": launch[3],
                    "steps_per_launch": spl,
                    **({"kernel": "row-marching", "group_rows": temporal[2],
