@@ -217,7 +217,7 @@ int dmrt_load_state(dmrt_cavity *h, const void *host, size_t bytes);
  * contiguous tiles to each of the 8 accelerator dies), graph_steps >= 0
  * (steps per captured graph; 0 = never capture).  Defaults at creation:
  * 256 x 1, die-aware order, graphs of 60 steps (a multiple of every
- * steps-per-launch K).  Results do not depend on the launch shape. */
+ * steps-per-launch K offered).  Results do not depend on the launch shape. */
 int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
                     int graph_steps);
 
@@ -246,9 +246,13 @@ int dmrt_set_temporal(dmrt_cavity *h, int steps_per_launch, int tile_rows);
  * row of its next iteration from global memory one iteration ahead.
  * (K, group_rows) in {(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3),
  * (4, 4), (6, 2)} (the LDS rings, (K - 1) x 14 x (group_rows + 2) x 64
- * elements, fit 160 KB in both precisions); chunk_rows >= 1, or 0 to pick the largest chunk that keeps one
- * launch's workgroups resident on the device at once.  DMRT_BC_CAVITY only
- * (EINVAL otherwise).  Results are identical to single steps.
+ * elements, fit 160 KB in both precisions); chunk_rows >= 1 (clamped to n),
+ * or 0 to pick the largest chunk that keeps one launch's workgroups
+ * resident on the device at once.  DMRT_BC_CAVITY only (EINVAL otherwise).
+ * Results are identical to single steps.  The adjoint's forward run uses
+ * the same launches, except in the objective window, where it takes the
+ * tile form's Nusselt-accumulating launches when K <= 4 and single steps
+ * otherwise.
  * dmrt_set_temporal switches the marching off.  EHIP if the device query for
  * chunk_rows = 0 fails.  On MI355X with chunk_rows = 0: K = 4 with 3 rows
  * (FP32) or 4 rows (FP64) is the fastest at 1024^2, K = 6 with 2 rows at
