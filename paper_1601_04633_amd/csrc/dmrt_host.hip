@@ -773,7 +773,7 @@ int dmrt_set_temporal_march(dmrt_cavity* h, int steps_per_launch, int group_rows
         chunk = h->esz == sizeof(double)
                     ? march_chunk_auto<double>(h->n, steps_per_launch, group_rows, h->dev)
                     : march_chunk_auto<float>(h->n, steps_per_launch, group_rows, h->dev);
-    if (chunk <= 0) return DMRT_EHIP;
+    if (chunk <= 0) return record_hip(hipErrorInvalidValue, "occupancy query for the marching kernel");
     HIPCHK(hipStreamSynchronize(h->stream));
     drop_graphs(h);
     if (h->adj) { free_adjoint(h->adj); h->adj = nullptr; }
