@@ -47,9 +47,12 @@ def test_lbgk_multi_step_launch_equals_single_steps(precision):
     n = 70
     th0 = inputs.theta_noise(n, 5, amp=1e-2)
     out = []
-    for temporal in ((1, 10), (4, 16), (3, 10)):
+    for temporal in ((1, 10), (4, 16), (3, 10), ("march", 4, 3, 9), ("march", 6, 2, 0)):
         c = Cavity(n=n, Ra=1e4, Pr=0.005, precision=precision, collision="lbgk")
-        c.set_temporal(*temporal)
+        if temporal[0] == "march":
+            c.set_temporal_march(*temporal[1:])
+        else:
+            c.set_temporal(*temporal)
         c.set_theta(th0)
         c.step(61)
         out.append(c.raw_state())
