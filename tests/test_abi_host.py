@@ -90,6 +90,9 @@ def test_null_handle_calls_are_rejected():
     assert D.dmrt_get_fields(None, None, None, None, None) == D.DMRT_EINVAL
     assert D.dmrt_nusselt(None, 0, None, None) == D.DMRT_EINVAL
     assert D.dmrt_destroy(None) == D.DMRT_OK
+    assert D.dmrt_set_temporal(None, 4, 16) == D.DMRT_EINVAL
+    assert D.dmrt_set_temporal_march(None, 4, 3, 0) == D.DMRT_EINVAL
+    assert D.dmrt_get_temporal_march(None, None, None) == D.DMRT_EINVAL
     out = ctypes.c_void_p()
     p = D.make_params(n=2)
     assert D.dmrt_create(ctypes.byref(p), None, None, None, ctypes.byref(out)) == D.DMRT_EINVAL
