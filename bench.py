@@ -345,8 +345,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: the cavity path is single-GPU in this build "
-              "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library steps a cavity on one GPU "
+              "(sharding across GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
