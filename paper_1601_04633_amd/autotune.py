@@ -76,8 +76,10 @@ def _store_cache(key, value):
         pass
 
 
-def _timer(stream_ptr):
-    """Returns (start, stop) closures timing work on the handle's stream."""
+def _timer(stream_ptr, sync):
+    """Returns (start, stop) closures timing work on the handle's stream:
+    HIP events on that stream when its pointer is given, else host time
+    with sync() (the handle's own synchronisation) before the stop."""
     try:
         import torch
         ext = torch.cuda.ExternalStream(stream_ptr) if stream_ptr else None
@@ -101,6 +103,7 @@ def _timer(stream_ptr):
         t[0] = time.perf_counter()
 
     def stop():
+        sync()
         return time.perf_counter() - t[0]
     return start, stop
 
@@ -152,7 +155,7 @@ def tune_batch(batch, stream_ptr=None, min_steps=128, use_cache=True, verbose=Fa
                    "group": tuple(hit["group"])}
             apply_batch(batch, cfg)
             return cfg, hit.get("sec_per_step"), []
-    start, stop = _timer(stream_ptr)
+    start, stop = _timer(stream_ptr, batch.sync)
 
     def measure(cfg):
         apply_batch(batch, cfg)
@@ -190,7 +193,7 @@ def tune_cavity(cavity, stream_ptr=None, steps=256, use_cache=True, verbose=Fals
             apply_cavity(cavity, {"temporal": tuple(hit["temporal"]), "block": tuple(hit["block"]),
                                   "xcd_remap": hit["xcd_remap"]})
             return hit, hit.get("sec_per_step"), []
-    start, stop = _timer(stream_ptr)
+    start, stop = _timer(stream_ptr, cavity.sync)
 
     def measure(cfg):
         apply_cavity(cavity, cfg)
@@ -226,7 +229,7 @@ def tune_adjoint(cavity, nsteps=2000, avg_last=400, ckpt_every=500, stream_ptr=N
         if hit:
             cavity.adjoint_set_temporal(*hit["temporal"])
             return tuple(hit["temporal"]), hit.get("sec_per_step"), []
-    start, stop = _timer(stream_ptr)
+    start, stop = _timer(stream_ptr, cavity.sync)
     trials = []
     for kr in ADJOINT_SPACE:
         cavity.adjoint_set_temporal(*kr)

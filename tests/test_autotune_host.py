@@ -105,3 +105,13 @@ def test_search_spaces_only_hold_supported_pairs():
             assert tuple(kr[1:3]) in march_ok, kr
         else:
             assert tuple(kr) in ok, kr
+
+
+def test_host_timer_waits_for_the_handle():
+    """Without a stream pointer the timer uses host time and calls the
+    handle's synchronisation before reading it, so queued work is counted."""
+    calls = []
+    start, stop = autotune._timer(None, lambda: calls.append(1))
+    start()
+    t = stop()
+    assert calls == [1] and t >= 0
