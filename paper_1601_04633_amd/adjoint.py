@@ -25,14 +25,18 @@ class NuObjective(torch.autograd.Function):
         ctx.cavity = cavity
         ctx.shapes = (theta_w.shape, theta0.shape)
         ctx.devices = (theta_w.device, theta0.device)
+        ctx.dtypes = (theta_w.dtype, theta0.dtype)
         return torch.tensor(J, dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, grad_out):
         gw, g0 = ctx.cavity.adjoint_backward()
         s = float(grad_out)
-        gw_t = torch.from_numpy(np.ascontiguousarray(gw * s)).reshape(ctx.shapes[0]).to(ctx.devices[0])
-        g0_t = torch.from_numpy(np.ascontiguousarray(g0 * s)).reshape(ctx.shapes[1]).to(ctx.devices[1])
+        # gradients in the inputs' own dtype and device (computed in FP64)
+        gw_t = torch.from_numpy(np.ascontiguousarray(gw * s)).reshape(ctx.shapes[0]).to(
+            device=ctx.devices[0], dtype=ctx.dtypes[0])
+        g0_t = torch.from_numpy(np.ascontiguousarray(g0 * s)).reshape(ctx.shapes[1]).to(
+            device=ctx.devices[1], dtype=ctx.dtypes[1])
         return gw_t, g0_t, None, None, None, None
 
 

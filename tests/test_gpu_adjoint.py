@@ -155,9 +155,32 @@ def test_autograd_function():
     J = nu_objective(tw, t0, c, N, K, C)
     (2.0 * J).backward()
     Jd, gw, g0 = _gpu_grad(n, 1e4, 0.01, tw.detach().numpy(), t0.detach().numpy(), N, K, C)
-    assert float(J) == Jd
+    assert float(J.detach()) == Jd
     assert np.array_equal(tw.grad.numpy(), 2.0 * gw)
     assert np.array_equal(t0.grad.numpy(), 2.0 * g0)
+    c.close()
+
+
+def test_autograd_function_float32_and_device_inputs():
+    """FP32 leaf tensors on the GPU get FP32 gradients on the GPU (the
+    values of the FP64 adjoint rounded once)."""
+    import torch
+    from paper_1601_04633_amd.adjoint import nu_objective
+    n, N, K, C = 16, 60, 20, 20
+    tw64 = inputs.hot_wall_profile(n, 31)
+    t064 = inputs.theta_noise(n, 32, amp=1e-2)
+    tw = torch.tensor(tw64, dtype=torch.float32, device="cuda", requires_grad=True)
+    t0 = torch.tensor(t064, dtype=torch.float32, device="cuda", requires_grad=True)
+    c = _cavity(n, 1e4, 0.01)
+    J = nu_objective(tw, t0, c, N, K, C)
+    J.backward()
+    c.close()
+    assert tw.grad.dtype == torch.float32 and tw.grad.device.type == "cuda"
+    assert t0.grad.dtype == torch.float32 and t0.grad.device.type == "cuda"
+    _, gw, g0 = _gpu_grad(n, 1e4, 0.01, tw.detach().cpu().double().numpy(),
+                          t0.detach().cpu().double().numpy(), N, K, C)
+    assert np.array_equal(tw.grad.cpu().numpy(), gw.astype(np.float32))
+    assert np.array_equal(t0.grad.cpu().numpy(), g0.astype(np.float32))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
