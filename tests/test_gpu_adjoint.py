@@ -110,10 +110,19 @@ def test_fp64_adjoint_against_oracle_finite_differences(oracle_mod):
     rel_a = np.abs(adj - got) / np.abs(got)
     print(f"[adjoint] fd (theta_w, directions; h 1e-6): max rel err {rel_a.max():.3e}", flush=True)
     assert rel_a.max() <= 1e-6, rel_a.max()
-    # (b) 64 initial-field entries.  After 10,000 steps these derivatives are
+    # (b) the initial field.  After 10,000 steps these derivatives are
     # 1e-9..2e-5, below the round-off of a central difference at h = 1e-6;
-    # J is linear in theta0 to ~1e-9 at h = 1e-2, whose round-off floor is
-    # ~2e-13 absolute.
+    # J is linear in theta0 to ~1e-9 at h = 1e-2, where the round-off floor
+    # of a difference is ~2e-13 absolute.  Dense random directions (whose
+    # derivatives are far above that floor) must agree to 1e-6 relative,
+    # and 64 single entries as a vector (normwise) to 1e-6.
+    dirs = [(np.zeros(n), d0) for d0 in inputs.random_directions((n, n), 4, 79)]
+    adj = np.array([(g0 * d0).sum() for _, d0 in dirs])
+    got = np.array(fd.directional_derivatives(n, Ra, Pr, tw, t0, N, K, dirs, h=1e-2, workers=16))
+    rel_d = np.abs(adj - got) / np.abs(got)
+    print(f"[adjoint] fd (theta0 directions; h 1e-2): |d| {np.abs(got).min():.2e}..{np.abs(got).max():.2e}, "
+          f"max rel err {rel_d.max():.3e}", flush=True)
+    assert rel_d.max() <= 1e-6, rel_d
     dirs, adj = [], []
     for idx in rng.choice(n * n, size=64, replace=False):
         d0 = np.zeros(n * n)
@@ -123,10 +132,37 @@ def test_fp64_adjoint_against_oracle_finite_differences(oracle_mod):
     got = np.array(fd.directional_derivatives(n, Ra, Pr, tw, t0, N, K, dirs, h=1e-2, workers=16))
     adj = np.array(adj)
     err = np.abs(adj - got)
-    print(f"[adjoint] fd (theta0; h 1e-2): max rel err {(err / np.abs(got)).max():.3e}, "
-          f"max abs err {err.max():.3e}, |grad| {np.abs(got).min():.2e}..{np.abs(got).max():.2e}",
-          flush=True)
-    assert np.all(err <= 1e-6 * np.abs(got) + 1e-12)
+    print(f"[adjoint] fd (theta0 entries; h 1e-2): normwise rel err "
+          f"{np.linalg.norm(err) / np.linalg.norm(got):.3e}, max abs err {err.max():.3e}, "
+          f"|grad| {np.abs(got).min():.2e}..{np.abs(got).max():.2e}", flush=True)
+    assert np.linalg.norm(err) <= 1e-6 * np.linalg.norm(got)
+
+
+def test_fp64_adjoint_config_instance_against_reference():
+    """The same 32^2, 10,000-step instance against the CPU FP64 reference
+    adjoint (tests/golden/adjoint_ref_32.json, written from
+    oracle/torch_ref.py alone): J to 1e-12, both gradients to 1e-10
+    relative (normwise), with one checkpoint every 500 steps and four
+    adjoint steps per backward launch."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "adjoint_ref_32.json")))
+    n, Ra, Pr, N, K = gold["n"], gold["Ra"], gold["Pr"], gold["steps"], gold["avg_last"]
+    tw = inputs.hot_wall_profile(n, gold["hot_wall_seed"])
+    t0 = inputs.theta_noise(n, gold["theta0_seed"])
+    rw = np.array(gold["dJ_dthetaw"])
+    r0 = np.array(gold["dJ_dtheta0"]).reshape(n, n)
+    for temporal in ((1, 10), (4, 12)):
+        c = _cavity(n, Ra, Pr)
+        c.adjoint_set_temporal(*temporal)
+        c.set_hot_wall(tw)
+        c.set_theta(t0)
+        Jg, gw, g0 = c.adjoint_nu(N, K, 500)
+        c.close()
+        print(f"[adjoint] 32^2 x 10000 vs reference, backward {temporal}: J {abs(Jg / gold['J'] - 1):.2e}, "
+              f"dJ/dtheta_w {rel(gw, rw):.2e}, dJ/dtheta0 {rel(g0, r0):.2e}", flush=True)
+        assert abs(Jg - gold["J"]) <= 1e-12 * abs(gold["J"])
+        assert rel(gw, rw) <= 1e-10 and rel(g0, r0) <= 1e-10
 
 
 def test_fp32_adjoint_config_against_fp64():
@@ -140,9 +176,10 @@ def test_fp32_adjoint_config_against_fp64():
     J64, w64, z64 = _gpu_grad(n, Ra, Pr, tw, t0, N, K, C, "fp64")
     print(f"[adjoint] fp32 vs fp64: J {abs(J32 - J64) / abs(J64):.2e}, dJ/dtheta_w "
           f"{rel(w32, w64):.2e}, dJ/dtheta0 {rel(z32, z64):.2e}", flush=True)
+    # measured: 1.1e-5, 9.4e-6, 5.2e-8; bars about ten times those
     assert abs(J32 - J64) <= 1e-4 * abs(J64)
-    assert rel(w32, w64) <= 1e-3
-    assert rel(z32, z64) <= 1e-2
+    assert rel(w32, w64) <= 1e-4
+    assert rel(z32, z64) <= 1e-6
 
 
 def test_autograd_function():
@@ -251,3 +288,65 @@ def test_multi_step_backward_against_reference():
     Jr, rw, r0 = Reference(n, 1e4, 0.01).gradient(tw, t0, N, K, segment=100)
     assert abs(Jg - Jr) <= 1e-12 * abs(Jr)
     assert rel(gw, rw) <= 1e-10 and rel(g0, r0) <= 1e-10
+
+
+def test_interleaved_objectives_on_one_cavity():
+    """Two objectives recorded on one cavity before one backward over their
+    sum: each gets the gradient of its own forward run (bitwise those of
+    separate cavities), and a hot-wall change between a forward and its
+    backward does not leak into the gradient."""
+    import torch
+    from paper_1601_04633_amd.adjoint import nu_objective
+    n, N, K, C = 24, 200, 50, 40
+    tw1 = torch.tensor(inputs.hot_wall_profile(n, 41), requires_grad=True)
+    t01 = torch.tensor(inputs.theta_noise(n, 42, amp=1e-2), requires_grad=True)
+    tw2 = torch.tensor(inputs.hot_wall_profile(n, 43, amp=3e-2), requires_grad=True)
+    t02 = torch.tensor(inputs.theta_noise(n, 44, amp=2e-2), requires_grad=True)
+    c = _cavity(n, 1e4, 0.01)
+    J1 = nu_objective(tw1, t01, c, N, K, C)
+    J2 = nu_objective(tw2, t02, c, N, K, C)
+    (J1 + 3.0 * J2).backward()
+    r1 = _gpu_grad(n, 1e4, 0.01, tw1.detach().numpy(), t01.detach().numpy(), N, K, C)
+    r2 = _gpu_grad(n, 1e4, 0.01, tw2.detach().numpy(), t02.detach().numpy(), N, K, C)
+    assert float(J1.detach()) == r1[0] and float(J2.detach()) == r2[0]
+    assert np.array_equal(tw1.grad.numpy(), r1[1]) and np.array_equal(t01.grad.numpy(), r1[2])
+    assert np.array_equal(tw2.grad.numpy(), 3.0 * r2[1]) and np.array_equal(t02.grad.numpy(), 3.0 * r2[2])
+    # a wall change between forward and backward
+    tw3 = torch.tensor(inputs.hot_wall_profile(n, 45), requires_grad=True)
+    J3 = nu_objective(tw3, t01.detach().clone(), c, N, K, C)
+    c.set_hot_wall(inputs.hot_wall_profile(n, 46))
+    J3.backward()
+    r3 = _gpu_grad(n, 1e4, 0.01, tw3.detach().numpy(), t01.detach().numpy(), N, K, C)
+    assert np.array_equal(tw3.grad.numpy(), r3[1])
+    c.close()
+
+
+def test_backward_refused_after_invalidating_calls():
+    """dmrt_adjoint_backward is refused (EINVAL) once the wall, the initial
+    field or the state has been replaced since the forward run, and the
+    generation counter reports it; stepping the handle does not."""
+    from paper_1601_04633_amd.dmrt import DmrtError
+    n, N, K, C = 16, 40, 10, 10
+    tw = inputs.hot_wall_profile(n, 47)
+    t0 = inputs.theta_noise(n, 48, amp=1e-2)
+    c = _cavity(n, 1e4, 0.01)
+    assert c.adjoint_generation() == 0
+    blob = c.save_state()
+    gens = []
+    for spoil in (lambda: c.set_hot_wall(tw), lambda: c.set_theta(t0), lambda: c.load_state(blob),
+                  lambda: c.set_temporal(2, 6), None):
+        c.set_hot_wall(tw)
+        c.set_theta(t0)
+        c.adjoint_forward(N, K, C)
+        gens.append(c.adjoint_generation())
+        if spoil is None:
+            c.step(7)
+            assert c.adjoint_generation() == gens[-1]
+            c.adjoint_backward()
+        else:
+            spoil()
+            assert c.adjoint_generation() == 0
+            with pytest.raises(DmrtError):
+                c.adjoint_backward()
+    assert gens == [1, 2, 3, 4, 5]
+    c.close()
