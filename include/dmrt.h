@@ -297,8 +297,23 @@ int dmrt_adjoint_forward(dmrt_cavity *h, long nsteps, long avg_last, long ckpt_e
 
 /* Backward run after dmrt_adjoint_forward: dJ_dthetaw (n doubles) and
  * dJ_dtheta0 (n*n doubles, y-major), either may be NULL.  The parameter
- * gradient is accumulated in FP64 on the device.  Synchronises. */
+ * gradient is accumulated in FP64 on the device.  Synchronises.  EINVAL when
+ * no forward run is stored, or when it no longer matches the handle:
+ * dmrt_set_hot_wall, dmrt_set_theta, dmrt_set_equilibrium or
+ * dmrt_load_state since the last dmrt_adjoint_forward (the backward would
+ * linearise about another wall or initial field), or a launch-mode call
+ * that released the adjoint buffers (dmrt_set_launch, dmrt_set_temporal,
+ * dmrt_set_temporal_march, dmrt_adjoint_set_temporal,
+ * dmrt_adjoint_release).  Stepping the handle does not affect it. */
 int dmrt_adjoint_backward(dmrt_cavity *h, double *dJ_dthetaw, double *dJ_dtheta0);
+
+/* Generation of the forward run that the next dmrt_adjoint_backward would
+ * differentiate: 1 for the handle's first successful dmrt_adjoint_forward,
+ * increasing by one with each later one; 0 when no forward run is stored
+ * or it was invalidated (see dmrt_adjoint_backward).  Lets a caller that
+ * keeps several objectives of one handle check that the stored run is its
+ * own.  Host only. */
+int dmrt_adjoint_generation(const dmrt_cavity *h, long *gen);
 
 /* dmrt_adjoint_forward followed by dmrt_adjoint_backward. */
 int dmrt_adjoint_nu(dmrt_cavity *h, long nsteps, long avg_last, long ckpt_every, double *J,

@@ -49,6 +49,7 @@ struct AdjointState {
     int* n0_table = nullptr;     // nseg
     int win_start = 0;
     bool forward_done = false;
+    long gen = 0;                // handle generation of the stored forward run
     double J = 0.0;
     // graphs: forward units (plain / Nusselt-accumulating) by parity, and a
     // full backward segment by lambda parity
@@ -79,6 +80,11 @@ void free_adjoint(AdjointState* a)
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete a;
+}
+
+void invalidate_adjoint(AdjointState* a)
+{
+    if (a) a->forward_done = false;
 }
 
 }  // namespace dmrt
@@ -472,8 +478,17 @@ int dmrt_adjoint_forward(dmrt_cavity* h, long nsteps, long avg_last, long ckpt_e
     if (h->p.bc_mode != DMRT_BC_CAVITY || !h->theta0_valid) return DMRT_EINVAL;
     if (!(h->p.theta_hot - h->p.theta_cold > 0.0)) return DMRT_EINVAL;
     if (ckpt_every > nsteps) ckpt_every = nsteps;
-    return h->esz == 8 ? forward_t<double>(h, nsteps, avg_last, ckpt_every, J)
-                       : forward_t<float>(h, nsteps, avg_last, ckpt_every, J);
+    const int rc = h->esz == 8 ? forward_t<double>(h, nsteps, avg_last, ckpt_every, J)
+                               : forward_t<float>(h, nsteps, avg_last, ckpt_every, J);
+    if (rc == DMRT_OK) h->adj->gen = ++h->adj_gen;
+    return rc;
+}
+
+int dmrt_adjoint_generation(const dmrt_cavity* h, long* gen)
+{
+    if (!h || !gen) return DMRT_EINVAL;
+    *gen = h->adj && h->adj->forward_done ? h->adj->gen : 0;
+    return DMRT_OK;
 }
 
 int dmrt_adjoint_backward(dmrt_cavity* h, double* dJ_dthetaw, double* dJ_dtheta0)

@@ -438,6 +438,7 @@ int dmrt_set_equilibrium(dmrt_cavity* h, const double* drho, const double* U, co
         if (check_host_array(a, nn)) return DMRT_EINVAL;
     DeviceGuard g(h->dev);
     if (!g.ok) return record_hip(hipErrorInvalidDevice, "hipSetDevice");
+    invalidate_adjoint(h->adj);   // the gradient problem's initial field changes
     int rc = ensure_scratch(h);
     if (rc) return rc;
     const double* dptr[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -479,6 +480,7 @@ int dmrt_set_hot_wall(dmrt_cavity* h, const double* theta_w)
     if (!h || !theta_w) return DMRT_EINVAL;
     if (check_host_array(theta_w, h->n)) return DMRT_EINVAL;
     DeviceGuard g(h->dev);
+    invalidate_adjoint(h->adj);   // the backward differentiates about the forward's wall
     h->thw_host.assign(theta_w, theta_w + h->n);
     return upload_hot_wall(h);
 }
@@ -711,6 +713,7 @@ int dmrt_load_state(dmrt_cavity* h, const void* host, size_t bytes)
     std::memcpy(thw.data(), in + sizeof hdr, h->n * sizeof(double));
     if (check_host_array(thw.data(), h->n)) return DMRT_EINVAL;
     HIPCHK(hipStreamSynchronize(h->stream));
+    invalidate_adjoint(h->adj);
     h->thw_host = thw;
     int rc = upload_hot_wall(h);
     if (rc) return rc;

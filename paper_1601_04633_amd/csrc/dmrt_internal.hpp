@@ -42,6 +42,9 @@ void set_last_error(const char* msg);
 
 struct AdjointState;          // dmrt_adjoint.hip
 void free_adjoint(AdjointState* a);
+// Marks the stored forward run as no longer matching the handle (its hot
+// wall, initial field or state changed): the next backward is refused.
+void invalidate_adjoint(AdjointState* a);
 
 }  // namespace dmrt
 
@@ -89,6 +92,7 @@ struct dmrt_cavity {
     double* theta0 = nullptr;         // n^2 doubles
     bool theta0_valid = false;
     dmrt::AdjointState* adj = nullptr;
+    long adj_gen = 0;                 // successful dmrt_adjoint_forward calls
 };
 
 

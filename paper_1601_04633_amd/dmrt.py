@@ -104,6 +104,7 @@ _SIGS = {
     "dmrt_adjoint_backward": [_vp, _dp, _dp],
     "dmrt_adjoint_nu": [_vp, _c_long, _c_long, _c_long, _dp, _dp, _dp],
     "dmrt_adjoint_release": [_vp],
+    "dmrt_adjoint_generation": [_vp, ctypes.POINTER(_c_long)],
     "dmrt_adjoint_set_temporal": [_vp, _c_int, _c_int],
     "dmrt_batch_create": [_P, _c_int, _vp, ctypes.POINTER(_vp)],
     "dmrt_batch_set_theta": [_vp, _c_int, _dp],
@@ -338,6 +339,12 @@ class Cavity:
         check(dmrt_adjoint_nu(self._h, int(nsteps), int(avg_last), int(ckpt_every), ctypes.byref(J),
                               _ptr(gw), _ptr(g0)), "dmrt_adjoint_nu")
         return J.value, gw, g0.reshape(self.n, self.n)
+
+    def adjoint_generation(self):
+        """Generation of the stored forward run (0: none usable)."""
+        g = ctypes.c_long(0)
+        check(dmrt_adjoint_generation(self._h, ctypes.byref(g)), "dmrt_adjoint_generation")
+        return g.value
 
     def adjoint_release(self):
         check(dmrt_adjoint_release(self._h), "dmrt_adjoint_release")
