@@ -181,7 +181,10 @@ def tune_batch(batch, stream_ptr=None, min_steps=128, use_cache=True, verbose=Fa
 
 def tune_cavity(cavity, stream_ptr=None, steps=256, use_cache=True, verbose=False):
     """Pick the fastest single-cavity launch shape; leaves it applied."""
-    key = f"cavity|{_arch()}|{'fp64' if cavity.params.precision == 1 else 'fp32'}|{cavity.n}"
+    # the search space depends on the wall configuration (K-step forms exist
+    # for the cavity only), so it is part of the key
+    key = (f"cavity|{_arch()}|{'fp64' if cavity.params.precision == 1 else 'fp32'}|{cavity.n}"
+           f"|bc{cavity.params.bc_mode}")
     if cavity.params.bc_mode != 0:
         space = {k: v for k, v in CAVITY_SPACE.items() if k != "temporal"}
         space["temporal"] = [(1, 10)]

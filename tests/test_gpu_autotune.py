@@ -44,6 +44,24 @@ def test_tune_cavity_then_step_bitwise(cache, n):
     c2.close()
 
 
+def test_tune_periodic_after_cavity_at_same_size(cache):
+    """A cached cavity-mode entry (which may hold a K-step form) is not
+    applied to a periodic box of the same size: each wall configuration is
+    tuned and cached under its own key."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    n = 64
+    c = Cavity(n=n, Ra=1e4, Pr=0.01, precision="fp32")
+    c.set_theta(inputs.theta_noise(n, 8, amp=1e-2))
+    autotune.tune_cavity(c, steps=24)
+    c.close()
+    p = Cavity(n=n, Ra=1e4, Pr=0.01, precision="fp32", bc_mode=1, gbeta_override=1e-4)
+    p.set_theta(inputs.theta_noise(n, 9, amp=1e-2))
+    best, t, trials = autotune.tune_cavity(p, steps=24)
+    assert trials and tuple(best["temporal"]) == (1, 10)
+    p.step(10)
+    p.close()
+
+
 def test_tune_batch_then_step_bitwise(cache):
     from paper_1601_04633_amd.dmrt import Batch, Cavity
     members = [dict(n=40, Ra=1e4, Pr=0.01), dict(n=70, Ra=3e4, Pr=0.005)]
