@@ -58,7 +58,8 @@ def test_fp32_matches_fp64_on_oscillation_statistics(runs, case):
 
 def test_config_256_pr0005_fp32_vs_fp64():
     """256^2, Ra 1e4, Pr 0.005, 200,000 steps in FP32 and FP64: the Nusselt
-    series statistics agree within 1 % and the final fields within 1e-4."""
+    series statistics agree within 1 %, the final hot-wall Nu within 1e-4
+    and the final U, V, theta fields within 1e-5 (field-norm relative)."""
     from paper_1601_04633_amd import inputs
     from paper_1601_04633_amd.analysis import oscillation_stats
     from paper_1601_04633_amd.dmrt import Cavity
@@ -79,5 +80,6 @@ def test_config_256_pr0005_fp32_vs_fp64():
     assert abs(s32["mean"] / s64["mean"] - 1) < 0.01
     assert abs(s32["peak_to_peak_window"] / s64["peak_to_peak_window"] - 1) < 0.01
     assert abs(n32 / n64 - 1) < 1e-4
+    # measured 1.1e-7 (U), 1.3e-7 (V), 1.8e-7 (theta): the FP32 path's bar
     for nm, e in ferr.items():
-        assert e < 1e-4, (nm, e)
+        assert e < 1e-5, (nm, e)
