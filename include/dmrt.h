@@ -204,6 +204,25 @@ int dmrt_nu_series_read(dmrt_cavity *h, double *out, long *count);
  * if any distribution is NaN or Inf.  Synchronises. */
 int dmrt_residual(dmrt_cavity *h, double *res_theta, double *res_u);
 
+/* dmrt_residual for callers that cannot allocate device memory (serving
+ * loops, harnesses that forbid hipMalloc): the same quantities and the same
+ * kernels, with no hipMalloc or hipFree in the call.
+ *  ref: caller-owned device memory of 3 n^2 doubles (8-byte aligned) with
+ *    the previous theta, U and V (Eq. 33 velocity), y-major; read, then
+ *    overwritten with the current fields.  Zero it before the first call
+ *    (which then returns 1 and 1).  The caller keeps its size right: the
+ *    library cannot check it.
+ *  The FP64 partial sums live in a library-owned device array of fixed size
+ *  (at most 1024 workgroup partials: 41,000 bytes on each device the call
+ *  runs on, held until the process ends).  The reduction uses at most 1024
+ *  workgroups whatever n, so every cavity fits; EINVAL if it would not.
+ *  Every call on one device shares that array and leaves its last contents
+ *  there: calls that overlap on one device (several host threads or
+ *  streams) race and must be serialised by the caller.
+ * Returns DMRT_ENONFINITE as dmrt_residual.  EINVAL for NULL h or ref or a
+ * misaligned ref.  Synchronises the handle's stream. */
+int dmrt_residual_noalloc(dmrt_cavity *h, double *ref, double *res_theta, double *res_u);
+
 /* Host checkpoint of the complete state (distributions at the current step,
  * step counter, hot-wall profile).  dmrt_state_bytes gives the size;
  * dmrt_load_state requires a blob saved with the same n and precision and

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdmrt.so")
-SOURCES = ["dmrt_host.hip", "dmrt_batch.hip", "dmrt_adjoint.hip"]
+SOURCES = ["dmrt_host.hip", "dmrt_batch.hip", "dmrt_adjoint.hip", "dmrt_noalloc.hip"]
 HEADERS = ["dmrt_device.hpp", "dmrt_internal.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -91,6 +91,7 @@ _SIGS = {
     "dmrt_nu_series": [_vp, _c_int, _c_long],
     "dmrt_nu_series_read": [_vp, _dp, ctypes.POINTER(_c_long)],
     "dmrt_residual": [_vp, _dp, _dp],
+    "dmrt_residual_noalloc": [_vp, _vp, _dp, _dp],
     "dmrt_state_bytes": [_vp, ctypes.POINTER(_c_size)],
     "dmrt_save_state": [_vp, _vp, _c_size],
     "dmrt_load_state": [_vp, _vp, _c_size],
@@ -303,6 +304,15 @@ class Cavity:
         rc = dmrt_residual(self._h, ctypes.byref(rt), ctypes.byref(ru))
         if rc not in (DMRT_OK, DMRT_ENONFINITE):
             check(rc, "dmrt_residual")
+        return rt.value, ru.value, rc == DMRT_ENONFINITE
+
+    def residual_noalloc(self, ref_ptr):
+        """dmrt_residual_noalloc with the reference fields at device address
+        ref_ptr (3 n^2 doubles, caller-owned)."""
+        rt, ru = ctypes.c_double(0), ctypes.c_double(0)
+        rc = dmrt_residual_noalloc(self._h, ref_ptr, ctypes.byref(rt), ctypes.byref(ru))
+        if rc not in (DMRT_OK, DMRT_ENONFINITE):
+            check(rc, "dmrt_residual_noalloc")
         return rt.value, ru.value, rc == DMRT_ENONFINITE
 
     def save_state(self) -> bytes:
