@@ -248,7 +248,9 @@ int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
  * halo).  tile_rows in {4, 6, 10, 16} for K <= 2, {6, 10, 12, 14, 16} for
  * K = 3, {10, 12, 14, 16} for K = 4.  K >= 2 is available for
  * DMRT_BC_CAVITY only (EINVAL otherwise).  Results are identical to
- * single steps; Nusselt samples are still taken after every stride-th step.
+ * single steps; Nusselt samples are still taken after every stride-th step
+ * (a sample due on an intermediate step of a launch is taken by that launch,
+ * with the same value as after a single step).
  * Default at creation: K = 1.  On MI355X K = 4 with 16 rows is the fastest
  * tile shape from about 512^2 up, 12 rows below that; from 1024^2 up the
  * marching form (dmrt_set_temporal_march) is faster. */

@@ -186,7 +186,27 @@ struct StepArgs {
     int tiles_x, tiles;             // tile grid of the launch
     int xcd_remap;
     Coef<real> c;
+    // Nusselt samples inside a K-step launch: for every phase j (step t + j,
+    // 1 <= j < K) whose bit is set in samp_mask, the temperature sums of the
+    // post-collision g at x = 0 and x = 1 of every row go to
+    // samp[(j - 1) * 2 n + 2 y + x] (FP64, summed as the Nusselt kernel sums)
+    double* __restrict__ samp = nullptr;
+    int samp_mask = 0;
 };
+
+// Temperature sum of a node's post-collision g in FP64, in the order the
+// Nusselt kernels use, into the sample buffer for phase j when x is 0 or 1
+// (lanes left of the wall, x < 0, write nothing).
+template <typename real>
+__device__ __forceinline__ void samp_put(const StepArgs<real>& A, int j, int x, int y, const real (&g)[5])
+{
+    if (x == 0 || x == 1) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) t += double(g[i]);
+        A.samp[(j - 1) * 2 * A.n + 2 * y + x] = t;
+    }
+}
 
 // Maps the hardware workgroup id to a tile so that each of the 8 dies gets
 // a contiguous range of tiles (the dispatcher deals workgroups round-robin
@@ -760,6 +780,7 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
 #pragma unroll
             for (int i = 0; i < 5; ++i) A.gout[i * P + k] = g[i];
         }
+        if (!ALL && !NU && (A.samp_mask & 2) && own) samp_put<real>(A, 1, x, y, g);
     }
     if constexpr (NU) nu_row_add<real>(g, inside, own && x == 0, y, thw_d, acc);
     __syncthreads();
@@ -786,6 +807,7 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
 #pragma unroll
                 for (int i = 0; i < 5; ++i) go[i * P + k] = g[i];
             }
+            if (!ALL && !NU && (A.samp_mask & (1 << j)) && own) samp_put<real>(A, j, x, y, g);
         }
         __syncthreads();
     }
@@ -945,7 +967,7 @@ __device__ __forceinline__ void gather_cavity_walls(real thw_y, int n, int x, co
 // Per-wave constants of the row-marching kernel.
 template <typename real>
 struct MarchWave {
-    int j, r, x, lx, aj, aK, lo, hi, ymir;
+    int j, r, x, lx, aj, aK, lo, hi, ymir, y0, y1;
     bool xact, down;
     const real* rin;
     real* rout;
@@ -984,6 +1006,9 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
     if (act) {
         real th, ux, uy;
         collide<real>(cf, cg, A.c, th, ux, uy);
+        // a Nusselt sample due at this group's step: rows of this chunk only
+        if ((FIRST || w.j < K) && (A.samp_mask & (1 << w.j)) && y >= w.y0 && y < w.y1)
+            samp_put<real>(A, w.j, w.x, y, cg);
     }
     __syncthreads();
     if (act) {
@@ -1033,6 +1058,8 @@ __global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A,
     // time, at the end of both sweeps or at the start of both
     w.down = (tyt & 1) != 0;
     w.ymir = y0 + y1 - 1;
+    w.y0 = y0;
+    w.y1 = y1;
     w.xact = w.x >= 0 && w.x < n && w.lx >= w.j - 1 && w.lx <= kFootW - w.j;
     w.rin = lds + (w.j >= 2 ? (w.j - 2) * RING : 0);
     w.rout = lds + (w.j < K ? (w.j - 1) * RING : 0);
@@ -1367,6 +1394,34 @@ __global__ void __launch_bounds__(256) nusselt_kernel(
             ring[c % (unsigned long long)ring_cap] = avg;
             *ring_count = c + 1;
         }
+    }
+}
+
+// Hot-wall Nusselt sample from the temperature sums a K-step launch wrote
+// (t[2 y] at x = 0, t[2 y + 1] at x = 1): the per-row values and the
+// reduction of nusselt_block, so the sample equals what nusselt_kernel
+// gives for that step's state; appended to the ring.
+static __global__ void __launch_bounds__(256) nusselt_samp_kernel(
+    const double* __restrict__ t, int n, const double* __restrict__ thw, double H, double inv_dT,
+    double* __restrict__ ring, unsigned long long* __restrict__ ring_count, long ring_cap)
+{
+    __shared__ double part[4];
+    double acc = 0.0;
+    for (int y = threadIdx.x; y < n; y += blockDim.x) {
+        const double t0 = t[2 * y], t1 = t[2 * y + 1];
+        const double slope_in = (9.0 * t0 - t1 - 8.0 * thw[y]) * (1.0 / 3.0);
+        acc += -slope_in * H * inv_dT;
+    }
+    acc = wave_sum(acc);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) part[wid] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
+        const unsigned long long c = *ring_count;
+        ring[c % (unsigned long long)ring_cap] = s / n;
+        *ring_count = c + 1;
     }
 }
 

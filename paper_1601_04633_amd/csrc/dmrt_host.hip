@@ -202,27 +202,45 @@ int launch_nusselt(dmrt_cavity* h, hipStream_t s, int copy, int wall, double* lo
                                     : launch_nusselt_t<float>(h, s, copy, wall, local, avg, to_ring);
 }
 
+// Hot-wall Nusselt sample of an intermediate step of a K-step launch, from
+// the temperature sums it wrote, appended to the ring.
+int launch_nusselt_samp(dmrt_cavity* h, hipStream_t s, int j)
+{
+    const double dT = h->p.theta_hot - h->p.theta_cold;
+    const double inv_dT = dT != 0.0 ? 1.0 / dT : 1.0;
+    hipLaunchKernelGGL(nusselt_samp_kernel, dim3(1), dim3(256), 0, s, h->samp + (size_t)(j - 1) * 2 * h->n,
+                       h->n, h->thw_dbl, h->d.H, inv_dT, h->ring, h->ring_count, h->ring_cap);
+    HIPCHK(hipGetLastError());
+    return DMRT_OK;
+}
+
 // Enqueue `count` steps starting at copy `from` with Nu samples where due;
 // `base` is the step counter before the first of them.  Groups of K =
-// h->temporal steps run as one launch through LDS when enabled and no
-// sample falls inside the group.  *flips receives the number of launches
-// (each moves the state to the other copy).
+// h->temporal steps run as one launch through LDS when enabled; a sample
+// due inside a group is taken by that launch (the wall-column sums of the
+// step) and reduced right after it, in step order.  *flips receives the
+// number of launches (each moves the state to the other copy).
 int enqueue_steps(dmrt_cavity* h, hipStream_t s, int from, long base, long count, int* flips)
 {
     int c = from, nflip = 0;
     const int K = h->p.bc_mode == DMRT_BC_CAVITY ? h->temporal : 1;
     long i = 0;
     while (i < count) {
-        bool due_inside = false;
+        int mask = 0;
         if (h->series_stride > 0)
-            for (int j = 1; j < K; ++j) due_inside |= (base + i + j) % h->series_stride == 0;
+            for (int j = 1; j < K; ++j)
+                if ((base + i + j) % h->series_stride == 0) mask |= 1 << j;
         int rc;
-        if (K >= 2 && i + K <= count && !due_inside) {
+        if (K >= 2 && i + K <= count) {
             rc = h->esz == sizeof(double)
                      ? launch_stepk<double>(h, s, fptr<double>(h, c), gptr<double>(h, c),
-                                            fptr<double>(h, c ^ 1), gptr<double>(h, c ^ 1))
+                                            fptr<double>(h, c ^ 1), gptr<double>(h, c ^ 1), nullptr,
+                                            nullptr, h->samp, mask)
                      : launch_stepk<float>(h, s, fptr<float>(h, c), gptr<float>(h, c),
-                                           fptr<float>(h, c ^ 1), gptr<float>(h, c ^ 1));
+                                           fptr<float>(h, c ^ 1), gptr<float>(h, c ^ 1), nullptr,
+                                           nullptr, h->samp, mask);
+            for (int j = 1; j < K && !rc; ++j)
+                if (mask & (1 << j)) rc = launch_nusselt_samp(h, s, j);
             i += K;
         } else {
             rc = launch_step(h, s, c);
@@ -598,6 +616,7 @@ int dmrt_nu_series(dmrt_cavity* h, int stride, long cap)
     h->series_stride = stride;
     if (stride == 0) return DMRT_OK;
     if (!h->ring_count) HIPCHK(hipMalloc(&h->ring_count, sizeof(unsigned long long)));
+    if (!h->samp) HIPCHK(hipMalloc(&h->samp, (size_t)kMaxK * 2 * h->n * sizeof(double)));
     HIPCHK(hipMalloc(&h->ring, cap * sizeof(double)));
     h->ring_cap = cap;
     int rc = reset_series(h);
@@ -815,7 +834,7 @@ int dmrt_destroy(dmrt_cavity* h)
     if (h->own_bufs) { (void)hipFree(h->fbuf); (void)hipFree(h->gbuf); }
     if (h->adj) free_adjoint(h->adj);
     void* ptrs[] = {h->thw_real, h->thw_dbl, h->scratch, h->nu_buf, h->res_ref, h->res_part,
-                    h->ring, h->ring_count, h->theta0};
+                    h->ring, h->samp, h->ring_count, h->theta0};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);

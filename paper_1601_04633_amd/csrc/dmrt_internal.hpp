@@ -76,6 +76,7 @@ struct dmrt_cavity {
     double* res_part = nullptr;       // residual partials
     int res_blocks = 0;
     double* ring = nullptr;
+    double* samp = nullptr;           // Nusselt sample sums of K-step launches, kMaxK x 2 n doubles
     unsigned long long* ring_count = nullptr;
     long ring_cap = 0;
     int series_stride = 0;
@@ -127,6 +128,7 @@ inline bool valid_temporal(int k, int rows)
 #define DMRT_FOR_EACH_KB(X) X(2, 8) X(3, 2) X(3, 4) X(4, 1) X(4, 2) X(4, 3) X(4, 4) X(6, 2)
 
 constexpr long kLdsBytes = 160 * 1024;
+constexpr int kMaxK = 6;           // most steps per launch of any K-step form
 
 constexpr long march_lds_bytes(int k, int b, int esz)
 {
@@ -168,11 +170,12 @@ int march_chunk_auto(int n, int K, int B, int dev)
 // (h->march wave rows per step group, h->march_chunk rows per workgroup).
 template <typename real>
 int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
-                 real* gout)
+                 real* gout, double* samp = nullptr, int samp_mask = 0)
 {
     const int K = h->temporal, B = h->march, chunk = h->march_chunk;
     StepArgs<real> A;
     A.fin = fin; A.gin = gin; A.fout = fout; A.gout = gout;
+    A.samp = samp; A.samp_mask = samp_mask;
     A.thw = static_cast<const real*>(h->thw_real);
     A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
     const int W = kFootW - 2 * (K - 1);
@@ -197,15 +200,19 @@ int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
 // Launches K = h->temporal steps of the cavity from (fin, gin) to (fout, gout)
 // through LDS with footprint rows h->t_rows (K >= 2).  With acc non-null the
 // launch also adds each step's hot-wall Nusselt row sums to acc (FP64, n
-// entries; thw_d the FP64 wall temperatures).
+// entries; thw_d the FP64 wall temperatures).  samp_mask bit j (1 <= j < K):
+// the launch writes the wall-column temperature sums of step t + j to
+// samp + (j - 1) 2 n (see StepArgs).
 template <typename real>
 int launch_stepk(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
-                 real* gout, const double* thw_d = nullptr, double* acc = nullptr)
+                 real* gout, const double* thw_d = nullptr, double* acc = nullptr,
+                 double* samp = nullptr, int samp_mask = 0)
 {
-    if (h->march && !acc) return launch_stepm<real>(h, s, fin, gin, fout, gout);
+    if (h->march && !acc) return launch_stepm<real>(h, s, fin, gin, fout, gout, samp, samp_mask);
     const int K = h->temporal, R = h->t_rows;
     StepArgs<real> A;
     A.fin = fin; A.gin = gin; A.fout = fout; A.gout = gout;
+    A.samp = samp; A.samp_mask = samp_mask;
     A.thw = static_cast<const real*>(h->thw_real);
     A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
     const int W = kFootW - 2 * (K - 1), HO = R - 2 * (K - 1);

@@ -447,6 +447,39 @@ def test_marching_launch_equals_single_steps(precision, k, group):
         m.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("temporal", [(4, 16), (3, 12), ("march", 4, 3, 0), ("march", 6, 2, 0),
+                                      ("march", 4, 1, 9)])
+def test_nu_series_inside_multi_step_launches(precision, temporal):
+    """A Nusselt sample due on an intermediate step of a K-step launch is
+    taken by that launch (wall-column sums of the step, reduced after it):
+    the series equals that of single steps bitwise, for strides shorter
+    than, equal to, coprime with and longer than K, with graph replay, and
+    the state is unchanged by the sampling."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    n, steps = 100, 257
+    th0 = inputs.theta_noise(n, 77, amp=1e-2)
+    for stride in (1, 2, 3, 7, 10):
+        print(f"[parity] nu series inside {temporal} stride {stride} {precision}", flush=True)
+        out = []
+        for mode in (None, temporal):
+            c = Cavity(n=n, Ra=2e4, Pr=0.01, precision=precision)
+            if mode and mode[0] == "march":
+                c.set_temporal_march(*mode[1:])
+            elif mode:
+                c.set_temporal(*mode)
+            c.set_launch(256, 1, 1, 60)
+            c.set_theta(th0)
+            c.nu_series(stride, 400)
+            c.step(steps)
+            out.append((c.nu_series_read(), c.raw_state()))
+            c.close()
+        (sa, (fa, ga)), (sb, (fb, gb)) = out
+        assert len(sa) == steps // stride
+        np.testing.assert_array_equal(sa, sb)
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
 def test_marching_fp64_matches_oracle(oracle_mod):
     o, c = _pair(oracle_mod, 100, 1e4, 0.01)
     c.set_temporal_march(4, 4, 0)
