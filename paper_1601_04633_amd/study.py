@@ -31,8 +31,8 @@ def run_case(n, Ra, Pr, fo_total, fo_from, precision="fp32", Ma=0.1, paper_mode=
     d = c.derived()
     steps_per_fo = n * n / d["alpha"]
     steps = int(round(fo_total * steps_per_fo))
-    # four steps per launch (bitwise the same states; groups that hold a Nu
-    # sample run as single steps)
+    # four steps per launch (bitwise the same states; a Nu sample due inside
+    # a launch is taken by that launch)
     if n >= 1024:
         c.set_temporal_march(4, 3, 0)
     else:
