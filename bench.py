@@ -30,19 +30,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (D2Q9+D2Q5 node updates/s), % HBM roofline; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD published)
-WORDS_PER_NODE = 28            # 14 populations read + 14 written per node update
+# Vector-instruction issue peak without packed FP32: one wave64 VALU
+# instruction per 4 cycles on each of 256 CUs x 4 SIMDs at 2.4 GHz
+# (614.4 G wave instructions/s; 78.6 TFLOP/s if every one were an FMA).
+VALU_PEAK_GINSTR = 256 * 4 * 2.4 / 4
+WORDS_PER_NODE = 28            # 14 populations read + 14 written per node and launch
+# committed counter summaries, by (kernel, cavity side)
 TRAFFIC_FILES = {
-    "step_kernel<float, 0>": os.path.join(ROOT, "profiles", "step_kernel_cavity_1024_fp32_traffic.json"),
-    "stepk_kernel<float, 16, 4>": os.path.join(ROOT, "profiles",
-                                               "stepk_kernel_K4_R16_cavity_1024_fp32_traffic.json"),
-    "stepm_kernel<float, 4, 3>": os.path.join(ROOT, "profiles",
-                                              "stepm_kernel_K4_B3_cavity_1024_fp32_traffic.json"),
+    ("step_kernel<float, 0>", 1024): "step_kernel_cavity_1024_fp32_traffic.json",
+    ("stepk_kernel<float, 16, 4>", 1024): "stepk_kernel_K4_R16_cavity_1024_fp32_traffic.json",
+    ("stepm_kernel<float, 4, 3>", 1024): "stepm_kernel_K4_B3_cavity_1024_fp32_traffic.json",
+    ("stepm_kernel<float, 6, 2>", 2048): "stepm_kernel_K6_B2_cavity_2048_fp32_traffic.json",
+    ("stepm_kernel<double, 4, 4>", 1024): "stepm_kernel_K4_B4_cavity_1024_fp64_traffic.json",
 }
 # launch configuration timed by default (the fastest for this workload on
-# MI355X): four steps per launch through LDS, 64 x 16 footprints,
-# die-aware tile order, graphs of 60 steps
-# four steps per launch, workgroups of 4 x 3 wavefronts marching up chunks
-# of rows (chunk length chosen to keep one launch resident)
+# MI355X): four steps per launch, workgroups of 4 x 3 wavefronts marching
+# up chunks of rows (chunk length chosen to keep one launch resident),
+# die-aware order, graphs of 60 steps
 DEFAULT_TEMPORAL = ("march", 4, 3, 0)
 DEFAULT_LAUNCH = (256, 1, 1, 60)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_04633_amd", "csrc", f)
@@ -66,24 +70,66 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_summary(kernel):
-    """The committed counter summary of this kernel (HBM bytes per launch,
-    VALU busy fraction), or None when it is missing or was taken on a
-    different kernel source."""
+def counter_summary(kernel, n):
+    """The committed counter summary of this kernel at this cavity side
+    (calibrated HBM bytes per launch, VALU instructions per launch), or None
+    when it is missing or was taken on a different kernel source."""
+    name = TRAFFIC_FILES.get((kernel, n))
+    if name is None:
+        return None
     try:
-        with open(TRAFFIC_FILES[kernel]) as fh:
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
             t = json.load(fh)
-    except (OSError, ValueError, KeyError):
+    except (OSError, ValueError):
         return None
     if t.get("kernel_hash") != kernel_hash() or t.get("kernel") != kernel:
         return None
     return t
 
 
-def measured_traffic(bytes_alg_per_launch, kernel):
-    """HBM bytes per launch from the committed counter summary, or None."""
-    t = counter_summary(kernel)
-    return None if t is None else t.get("bytes_per_launch")
+def roofline(kernel, esz, n, spl, us_launch, counters):
+    """Roofline entry of one kernel launch advancing an n x n cavity by spl
+    steps in us_launch microseconds.
+
+    HBM: a launch must read and write every population of every node once,
+    whatever spl (the intermediate states of a K-step launch stay on chip):
+    28 words x n^2 algorithmic bytes per launch.  ALU: the wave64 vector
+    instructions a launch issues (SQ_INSTS_VALU of the committed counter
+    summary, which holds while the kernel source is unchanged) against the
+    issue peak.  `bound` is the one of the two closer to its peak; the other
+    is reported beside it.  effective_GBs is 28 words per node update (K n^2
+    node updates per launch) over the launch time: above the HBM peak for
+    K >= 2 because K - 1 of the K steps never leave the chip."""
+    t = us_launch * 1e-6
+    hbm_bytes = WORDS_PER_NODE * esz * n * n
+    hbm = {"achieved": round(hbm_bytes / t / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm_bytes / t / 1e9 / HBM_PEAK_GBS, 4),
+           "algorithmic_bytes_per_launch": hbm_bytes}
+    alu = None
+    traffic = None
+    if counters:
+        traffic = counters.get("bytes_per_launch")
+        vi = counters.get("valu_instructions_per_launch")
+        if vi:
+            alu = {"achieved": round(vi / t / 1e9, 1), "peak": VALU_PEAK_GINSTR, "unit": "Ginstr/s",
+                   "frac": round(vi / t / 1e9 / VALU_PEAK_GINSTR, 4),
+                   "valu_instructions_per_launch": vi,
+                   "valu_busy_frac_counters": counters.get("valu_busy_frac")}
+    main, other, bound = (alu, hbm, "alu") if alu and alu["frac"] > hbm["frac"] else (hbm, alu, "hbm")
+    out = {"bound": bound, "achieved": main["achieved"], "peak": main["peak"], "unit": main["unit"],
+           "frac": main["frac"], "traffic": traffic, "kernel": kernel,
+           "launch_us": round(us_launch, 3), "steps_per_launch": spl,
+           "node_updates_per_launch": spl * n * n,
+           "effective_GBs": round(WORDS_PER_NODE * esz * spl * n * n / t / 1e9, 1)}
+    out["hbm" if bound == "alu" else "alu"] = other
+    if bound == "hbm":
+        out["algorithmic_bytes_per_launch"] = hbm_bytes
+    else:
+        out["valu_instructions_per_launch"] = alu["valu_instructions_per_launch"]
+        out["valu_busy_frac_counters"] = alu["valu_busy_frac_counters"]
+    if traffic:
+        out["traffic_over_algorithmic"] = round(traffic / hbm_bytes, 4)
+    return out
 
 
 def parse_temporal(text):
@@ -117,10 +163,12 @@ def apply_temporal(c, temporal):
     return None
 
 
-def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601, temporal=None, info=None):
+def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601, temporal=None, info=None,
+                nu_stride=0):
     """Returns (ms total, MLUPS, avg ms per step, Nu) for `steps` steps timed
     with HIP events on the cavity's own stream; info (a dict) receives the
-    chunk rows of the row-marching kernel."""
+    chunk rows of the row-marching kernel.  nu_stride > 0 records the
+    hot-wall Nusselt series every nu_stride steps meanwhile."""
     import torch
     from paper_1601_04633_amd import inputs
     from paper_1601_04633_amd.dmrt import Cavity
@@ -133,6 +181,8 @@ def time_cavity(n, Ra, Pr, precision, steps, warmup, launch=None, seed=1601, tem
         if info is not None:
             info["chunk_rows"] = chunk
     c.set_theta(inputs.theta_noise(n, seed))
+    if nu_stride:
+        c.nu_series(nu_stride, (warmup + steps) // nu_stride + 8)
     c.step(warmup)
     c.sync()
     torch.cuda.synchronize()
@@ -207,13 +257,41 @@ def bench_batch(steps, single_steps, count=64, seed=4633, tune=True):
             "batch_steps_timed": steps, "single_steps_timed_each": single_steps,
             "batch_mlups": round(batch_mlups, 1), "one_by_one_mlups": round(single_mlups, 1),
             "batch_over_one_by_one": round(batch_mlups / single_mlups, 3),
-            "batch_hbm_frac": round(batch_mlups * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4),
+            "roofline": batch_roofline(batch_mlups, cfg),
             "schedule": {k: list(v) if isinstance(v, tuple) else v for k, v in cfg.items()} if cfg else None,
             "single_launch_by_side": {str(k): {"block": list(v["block"]), "xcd_remap": v["xcd_remap"],
                                                "steps_per_launch_rows": list(v["temporal"])}
                                       for k, v in tuned.items()},
             "dead_members": int((status != 0).sum()),
             "nu_hot_wall_mean": float(nu[np.isfinite(nu)].mean())}
+
+
+def batch_roofline(mlups, cfg):
+    """The batched launches move every population of every member once per
+    launch: 28 words x 4 B per node per launch, i.e. 112 / K B per node
+    update with K steps per launch."""
+    K = int(cfg["temporal"][0]) if cfg else 1
+    gbs = mlups * 1e6 * WORDS_PER_NODE * 4 / K / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"batch_stepk_kernel<float, {cfg['temporal'][1]}, {K}>" if K >= 2
+            else "batch_step_kernel<float>",
+            "bytes_per_node_update": WORDS_PER_NODE * 4 / K, "steps_per_launch": K,
+            "effective_GBs": round(mlups * 1e6 * WORDS_PER_NODE * 4 / 1e9, 1)}
+
+
+def adjoint_roofline(n, t_bwd_step, K, esz=4):
+    """Backward pass at K adjoint steps per launch, per adjoint step and
+    node: the forward state of that step is gathered (14 words), mu is read
+    and written once per launch (28 / K), and the fused recompute of the
+    older segment reads its input once per launch (14 / K) and stores every
+    state (14): 28 + 42 / K words."""
+    words = 28 + 42 / K
+    gbs = words * esz * n * n / t_bwd_step / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"adjk_fused_kernel<float, R, {K}>" if K >= 2 else "adj_fused_kernel<float>",
+            "bytes_per_adjoint_node_update": words * esz, "steps_per_launch": K}
 
 
 def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp32"):
@@ -269,6 +347,7 @@ def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp3
             "backward_over_forward": round(t_bwd / t_plain, 3),
             "forward_plus_backward_over_forward": round((t_fwd + t_bwd) / t_plain, 3),
             "ideal_backward_over_forward_bytes": 2.5,
+            "roofline": adjoint_roofline(n, t_bwd / N, int(bwd[0]), 8 if precision == "fp64" else 4),
             "J": J, "grad_theta_w_norm": float(np.linalg.norm(gw)),
             "grad_theta0_norm": float(np.linalg.norm(g0))}
 
@@ -366,24 +445,12 @@ def main():
                                          temporal=temporal, info=info)
     esz = 8 if prec == "fp64" else 4
     spl = steps_per_launch(temporal)        # node updates per node per launch
-    ms_launch = ms_step * spl
-    # algorithmic bytes: the 28 words (112 B FP32) a node update must move
-    # (14 populations in, 14 out) times the node updates one launch makes
-    # (K n^2 when a launch advances K steps).  A K-step launch keeps K - 1 of
-    # its steps in LDS, so its HBM traffic is only the per-launch minimum of
-    # 28 words per node; that minimum and the measured counter bytes are
-    # reported beside it.
-    node_updates = spl * n * n
-    alg_bytes = WORDS_PER_NODE * esz * node_updates
-    achieved = alg_bytes / (ms_launch * 1e-3) / 1e9
-    min_bytes = WORDS_PER_NODE * esz * n * n
-    min_gbs = min_bytes / (ms_launch * 1e-3) / 1e9
+    us_launch = ms_step * spl * 1e3
     kname = kernel_name(temporal, esz)
-    traffic = measured_traffic(alg_bytes, kname) if n == 1024 and prec == "fp32" else None
-    counters = counter_summary(kname) if n == 1024 and prec == "fp32" else None
-    log(f"main: {mlups:.1f} MLUPS, {achieved:.1f} GB/s algorithmic ({WORDS_PER_NODE * esz} B per node "
-        f"update), {min_gbs:.1f} GB/s of the per-launch HBM minimum, {ms_launch*1e3:.2f} us/launch, "
-        f"Nu {nu:.5f}")
+    roof = roofline(kname, esz, n, spl, us_launch, counter_summary(kname, n))
+    log(f"main: {mlups:.1f} MLUPS, {us_launch:.2f} us/launch, roofline {roof['bound']} "
+        f"{roof['achieved']} {roof['unit']} = {roof['frac']:.3f} of peak "
+        f"(effective {roof['effective_GBs']} GB/s at 112 B per node update), Nu {nu:.5f}")
 
     out = {
         "metric": METRIC,
@@ -402,22 +469,7 @@ def main():
                                f"Ma=0.1, walls +-0.5, {prec.upper()} fused collide-stream step, "
                                f"{spl} step(s) per launch",
                    "global_batch": 1, "nodes": n * n, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": kname,
-                     "bytes_per_node_update": WORDS_PER_NODE * esz,
-                     "node_updates_per_launch": node_updates,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "hbm_minimum_bytes_per_launch": min_bytes,
-                     "hbm_minimum_GBs": round(min_gbs, 1),
-                     "hbm_minimum_frac": round(min_gbs / HBM_PEAK_GBS, 4),
-                     "valu_busy_frac_counters": None if counters is None else counters.get("valu_busy_frac"),
-                     # VALU issue ceiling without packed FP32: one wave64
-                     # instruction per 4 cycles on each of 1,024 SIMDs at 2.4 GHz
-                     "valu_instructions_per_launch_counters":
-                         None if counters is None else counters.get("valu_instructions_per_launch"),
-                     "valu_peak_wave_instructions_per_s": 1024 * 2.4e9 / 4},
+        "roofline": roof,
         "launch": {"block": list(launch[:2]), "xcd_remap": launch[2], "graph_steps": launch[3],
                    "steps_per_launch": spl,
                    **({"kernel": "row-marching", "group_rows": temporal[2],
@@ -447,28 +499,27 @@ def main():
 
     if "extras" in sections:
         extras = {}
+        def extra(name, n_, prec_, steps_, warm_, temporal_):
+            _, m, ms_step_, _ = time_cavity(n_, Ra, Pr, prec_, steps_, warm_, launch, temporal=temporal_)
+            e = 8 if prec_ == "fp64" else 4
+            k = steps_per_launch(temporal_)
+            kn = kernel_name(temporal_, e)
+            extras[name] = {"mlups": round(m, 1),
+                            "roofline": roofline(kn, e, n_, k, ms_step_ * k * 1e3, counter_summary(kn, n_))}
+
         log("extra: fp64 same cavity, row-marching (4 steps, 4 x 4 wavefronts) and tile (4 steps, 16 rows)")
-        _, m64, _, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1200), 600, launch,
-                                   temporal=("march", 4, 4, 0))
-        extras["fp64_march_K4_B4_mlups"] = round(m64, 1)
-        extras["fp64_march_algorithmic_hbm_frac"] = round(m64 * 1e6 * 224 / 1e9 / HBM_PEAK_GBS, 4)
-        _, m64t, _, _ = time_cavity(n, Ra, Pr, "fp64", max(args.steps // 10, 1200), 600, launch,
-                                    temporal=(4, 16))
-        extras["fp64_tile_K4_R16_mlups"] = round(m64t, 1)
+        extra("fp64_march_K4_B4", n, "fp64", max(args.steps // 10, 1200), 600, ("march", 4, 4, 0))
+        extra("fp64_tile_K4_R16", n, "fp64", max(args.steps // 10, 1200), 600, (4, 16))
         log("extra: fp32 tile kernel (4 steps, 16 rows) and single steps")
-        _, mt, _, _ = time_cavity(n, Ra, Pr, prec, max(args.steps // 5, 2000), 500, launch,
-                                  temporal=(4, 16))
-        extras["fp32_tile_K4_R16_mlups"] = round(mt, 1)
-        _, m1, _, _ = time_cavity(n, Ra, Pr, prec, max(args.steps // 5, 2000), 500, launch,
-                                  temporal=(1, 10))
-        extras["fp32_single_step_mlups"] = round(m1, 1)
-        extras["fp32_single_step_hbm_frac"] = round(m1 * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4)
+        extra("fp32_tile_K4_R16", n, prec, max(args.steps // 5, 2000), 500, (4, 16))
+        extra("fp32_single_step", n, prec, max(args.steps // 5, 2000), 500, (1, 10))
+        log("extra: the benchmark's launch with the Nusselt series recorded every 10 steps")
+        _, mnu, _, _ = time_cavity(n, Ra, Pr, prec, max(args.steps // 5, 2000), 500, launch,
+                                   temporal=temporal, nu_stride=10)
+        extras["nu_series_stride10_mlups"] = round(mnu, 1)
         log("extra: 2048^2 fp32 control (state larger than the 256 MB last-level cache)")
-        _, m2k, _, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=("march", 6, 2, 0))
-        extras["fp32_2048_march_K6_B2_mlups"] = round(m2k, 1)
-        extras["fp32_2048_march_algorithmic_hbm_frac"] = round(m2k * 1e6 * 112 / 1e9 / HBM_PEAK_GBS, 4)
-        _, m2t, _, _ = time_cavity(2048, Ra, Pr, "fp32", 4800, 600, launch, temporal=(4, 16))
-        extras["fp32_2048_tile_K4_R16_mlups"] = round(m2t, 1)
+        extra("fp32_2048_march_K6_B2", 2048, "fp32", 4800, 600, ("march", 6, 2, 0))
+        extra("fp32_2048_tile_K4_R16", 2048, "fp32", 4800, 600, (4, 16))
         out["extras"] = extras
     if "batch" in sections:
         log("batch: 64-cavity Ra x Pr sweep vs one by one")
