@@ -1507,6 +1507,30 @@ __global__ void __launch_bounds__(256) batch_check_kernel(const CavityDev<real>*
     if (threadIdx.x == 0 && bad) atomicOr(&flags[blockIdx.y], 1);
 }
 
+// Watchdog of dmrt_step: the populations of the two isothermal-wall columns
+// (x = 0 and x = n - 1, all 14 planes).  A non-finite value anywhere in the
+// cavity reaches one of them within n steps (information moves one node per
+// step).  One workgroup; sets *flag (pinned host memory) when one is found.
+template <typename real>
+__global__ void __launch_bounds__(256) wall_check_kernel(const real* __restrict__ fs,
+                                                         const real* __restrict__ gs, int n, int pitch,
+                                                         int plane, int* __restrict__ flag)
+{
+    int bad = 0;
+    for (int t = threadIdx.x; t < 2 * n; t += blockDim.x) {
+        const int y = t >> 1, x = (t & 1) ? n - 1 : 0;
+        const int k = y * pitch + x;
+        real s = real(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) s += fabs(fs[i * plane + k]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) s += fabs(gs[i * plane + k]);
+        bad |= !isfinite(s);
+    }
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0 && bad) *flag = 1;
+}
+
 // ---------------------------------------------------------------------------
 // Residual / watchdog: per-block partial sums (FP64), then a final pass.
 // part[b*5 + {0..4}] = sum dtheta^2, sum theta^2, sum du^2, sum u^2, nonfinite

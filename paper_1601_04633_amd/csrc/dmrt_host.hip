@@ -439,6 +439,13 @@ int dmrt_create(const dmrt_params* p, void* ext_f, void* ext_g, void* hip_stream
     if ((e = hipMalloc(&h->thw_real, h->n * h->esz)) != hipSuccess) return fail(record_hip(e, "hipMalloc(thw)"));
     if ((e = hipMalloc(&h->thw_dbl, h->n * sizeof(double))) != hipSuccess) return fail(record_hip(e, "hipMalloc(thw)"));
     if ((e = hipMalloc(&h->nu_buf, (h->n + 1) * sizeof(double))) != hipSuccess) return fail(record_hip(e, "hipMalloc(nu)"));
+    {
+        void* nf = nullptr;
+        if ((e = hipHostMalloc(&nf, sizeof(int), hipHostMallocDefault)) != hipSuccess)
+            return fail(record_hip(e, "hipHostMalloc(watchdog flag)"));
+        h->nonfinite = static_cast<volatile int*>(nf);
+        *h->nonfinite = 0;
+    }
     if ((rc = upload_hot_wall(h))) return fail(rc);
     *out = h;
     rc = dmrt_set_theta(h, nullptr);
@@ -485,6 +492,7 @@ int dmrt_set_equilibrium(dmrt_cavity* h, const double* drho, const double* U, co
     h->step = 0;
     if ((rc = reset_series(h))) return rc;
     HIPCHK(hipStreamSynchronize(h->stream));
+    *h->nonfinite = 0;
     return DMRT_OK;
 }
 
@@ -503,11 +511,30 @@ int dmrt_set_hot_wall(dmrt_cavity* h, const double* theta_w)
     return upload_hot_wall(h);
 }
 
+static int launch_wall_check(dmrt_cavity* h)
+{
+    if (h->esz == sizeof(double))
+        hipLaunchKernelGGL((wall_check_kernel<double>), dim3(1), dim3(256), 0, h->stream,
+                           static_cast<const double*>(h->fbuf) + (size_t)h->cur * 9 * h->plane,
+                           static_cast<const double*>(h->gbuf) + (size_t)h->cur * 5 * h->plane, h->n,
+                           h->pitch, h->plane, const_cast<int*>(h->nonfinite));
+    else
+        hipLaunchKernelGGL((wall_check_kernel<float>), dim3(1), dim3(256), 0, h->stream,
+                           static_cast<const float*>(h->fbuf) + (size_t)h->cur * 9 * h->plane,
+                           static_cast<const float*>(h->gbuf) + (size_t)h->cur * 5 * h->plane, h->n,
+                           h->pitch, h->plane, const_cast<int*>(h->nonfinite));
+    HIPCHK(hipGetLastError());
+    return DMRT_OK;
+}
+
 int dmrt_step(dmrt_cavity* h, long nsteps)
 {
     if (!h || nsteps < 0) return DMRT_EINVAL;
     DeviceGuard g(h->dev);
     if (!g.ok) return record_hip(hipErrorInvalidDevice, "hipSetDevice");
+    // a watchdog check of an earlier call (finished by now or not) found a
+    // non-finite state: report it and enqueue nothing
+    if (*h->nonfinite) return DMRT_ENONFINITE;
     const int unit = graph_unit(h);
     long left = nsteps;
     while (left > 0) {
@@ -544,7 +571,7 @@ int dmrt_step(dmrt_cavity* h, long nsteps)
             left -= chunk;
         }
     }
-    return DMRT_OK;
+    return nsteps > 0 ? launch_wall_check(h) : DMRT_OK;
 }
 
 int dmrt_sync(dmrt_cavity* h)
@@ -552,7 +579,7 @@ int dmrt_sync(dmrt_cavity* h)
     if (!h) return DMRT_EINVAL;
     DeviceGuard g(h->dev);
     HIPCHK(hipStreamSynchronize(h->stream));
-    return DMRT_OK;
+    return *h->nonfinite ? DMRT_ENONFINITE : DMRT_OK;
 }
 
 int dmrt_get_step(dmrt_cavity* h, long* step)
@@ -748,6 +775,7 @@ int dmrt_load_state(dmrt_cavity* h, const void* host, size_t bytes)
     h->step = hdr[3];
     if ((rc = reset_series(h))) return rc;
     HIPCHK(hipStreamSynchronize(h->stream));
+    *h->nonfinite = 0;
     return DMRT_OK;
 }
 
@@ -837,6 +865,7 @@ int dmrt_destroy(dmrt_cavity* h)
                     h->ring, h->samp, h->ring_count, h->theta0};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    if (h->nonfinite) (void)hipHostFree(const_cast<int*>(h->nonfinite));
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;

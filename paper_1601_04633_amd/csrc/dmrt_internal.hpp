@@ -92,6 +92,9 @@ struct dmrt_cavity {
     // initial temperature of the last dmrt_set_theta (gradient problem)
     double* theta0 = nullptr;         // n^2 doubles
     bool theta0_valid = false;
+    // set by the watchdog kernel after a dmrt_step call found a non-finite
+    // value in a wall column (pinned host memory, written by the device)
+    volatile int* nonfinite = nullptr;
     dmrt::AdjointState* adj = nullptr;
     long adj_gen = 0;                 // successful dmrt_adjoint_forward calls
 };

@@ -295,6 +295,41 @@ def test_residual_and_watchdog():
     assert bad
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_step_watchdog_reports_nonfinite_state(precision):
+    """dmrt_step's watchdog (the two isothermal-wall columns, checked after
+    every call) reports a NaN planted in the interior once it has spread to
+    a wall: dmrt_sync returns DMRT_ENONFINITE, later dmrt_step calls return
+    it without enqueuing, and re-initialising clears it; a healthy run never
+    reports it."""
+    from paper_1601_04633_amd.dmrt import Cavity, DmrtError, DMRT_ENONFINITE
+    n = 40
+    c = Cavity(n=n, Ra=1e4, Pr=0.01, precision=precision)
+    c.set_temporal(4, 12)
+    c.set_theta(inputs.theta_noise(n, 16))
+    c.step(300)
+    c.sync()
+    esz = 8 if precision == "fp64" else 4
+    blob = bytearray(c.save_state())
+    # g plane 2 (index 9 + 2 of the 14), node (x, y) = (20, 17): interior
+    off = 8 * 8 + n * 8 + esz * ((9 + 2) * n * n + 17 * n + 20)
+    blob[off:off + esz] = np.array([np.nan], dtype=np.float64 if esz == 8 else np.float32).tobytes()
+    c.load_state(bytes(blob))
+    c.step(2)                          # the NaN has not reached a wall column yet
+    c.sync()
+    c.step(2 * n)
+    with pytest.raises(DmrtError) as e:
+        c.sync()
+    assert e.value.code == DMRT_ENONFINITE
+    with pytest.raises(DmrtError) as e:
+        c.step(10)
+    assert e.value.code == DMRT_ENONFINITE
+    c.set_theta(inputs.theta_noise(n, 16))
+    c.step(100)
+    c.sync()
+    c.close()
+
+
 def _host_residual(prev, now):
     """||theta_now - theta_prev|| / ||theta_now|| and the same for (U, V),
     from (U, V, theta) snapshots."""
