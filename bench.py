@@ -280,18 +280,25 @@ def batch_roofline(mlups, cfg):
             "effective_GBs": round(mlups * 1e6 * WORDS_PER_NODE * 4 / 1e9, 1)}
 
 
+def adjoint_words(K):
+    """Words moved per adjoint step and node at K adjoint steps per launch:
+    mu is read and written once per launch (28 / K), the linearisation
+    point (u, v, theta) of each step is read once (3); the fused recompute
+    of the older segment reads its input state and writes its output state
+    once per launch (28 / K) and stores the point of every step (3):
+    6 + 56 / K words (K = 1 is the single-step form)."""
+    return 6 + 56 / K
+
+
 def adjoint_roofline(n, t_bwd_step, K, esz=4):
-    """Backward pass at K adjoint steps per launch, per adjoint step and
-    node: the forward state of that step is gathered (14 words), mu is read
-    and written once per launch (28 / K), and the fused recompute of the
-    older segment reads its input once per launch (14 / K) and stores every
-    state (14): 28 + 42 / K words."""
-    words = 28 + 42 / K
+    """Backward pass at K adjoint steps per launch against HBM, with the
+    algorithmic words of adjoint_words(K) per adjoint step and node."""
+    words = adjoint_words(K)
     gbs = words * esz * n * n / t_bwd_step / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": f"adjk_fused_kernel<float, R, {K}>" if K >= 2 else "adj_fused_kernel<float>",
-            "bytes_per_adjoint_node_update": words * esz, "steps_per_launch": K}
+            "bytes_per_adjoint_node_update": round(words * esz, 2), "steps_per_launch": K}
 
 
 def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp32"):
@@ -346,7 +353,7 @@ def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp3
             "backward_us_per_step": round(t_bwd / N * 1e6, 3),
             "backward_over_forward": round(t_bwd / t_plain, 3),
             "forward_plus_backward_over_forward": round((t_fwd + t_bwd) / t_plain, 3),
-            "ideal_backward_over_forward_bytes": 2.5,
+            "backward_over_forward_bytes": round(adjoint_words(int(bwd[0])) / (28 / int(best["temporal"][0])), 3),
             "roofline": adjoint_roofline(n, t_bwd / N, int(bwd[0]), 8 if precision == "fp64" else 4),
             "J": J, "grad_theta_w_norm": float(np.linalg.norm(gw)),
             "grad_theta0_norm": float(np.linalg.norm(g0))}

@@ -310,11 +310,13 @@ int dmrt_destroy(dmrt_cavity *h);
  * only theta also qualifies).  Gradients with respect to the hot-wall
  * profile theta_w(y) (Eq. 45 and Eq. 18) and theta0.  Only DMRT_BC_CAVITY.
  * The forward stores a checkpoint every ckpt_every steps; the backward
- * recomputes each segment from its checkpoint and runs the hand-written
- * adjoint step kernel (the discrete adjoint of the step: the transposed
- * collision Jacobian at each node, then the transposed streaming and wall
- * map).  Device memory: (ceil(nsteps/ckpt_every) +
- * ckpt_every + 2) states of 14 n^2 elements, held until
+ * recomputes each segment from its checkpoint, keeping of every step only
+ * the point the collision Jacobian depends on (the u, v and theta of the
+ * pre-collision state), and runs the hand-written adjoint step kernel (the
+ * discrete adjoint of the step: the transposed collision Jacobian at each
+ * node, then the transposed streaming and wall map).  Device memory:
+ * ceil(nsteps/ckpt_every) + 4 states of 14 n^2 elements and 2 ckpt_every
+ * points of 3 n^2 elements (plus n^2 + 2 n doubles), held until
  * dmrt_adjoint_release or dmrt_destroy.
  * ------------------------------------------------------------------------ */
 

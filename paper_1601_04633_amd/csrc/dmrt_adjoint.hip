@@ -7,13 +7,16 @@
 // steps; the state is copied to a checkpoint every C steps, and on the last
 // K steps a variant of the step kernel accumulates each row's Nusselt sum in
 // FP64.  J = H / (3 dT n K) * sum over rows and window steps.
-// Backward: segments of C steps, newest first.  Each segment's states are
-// recomputed from its checkpoint into one of two segment buffers; the
-// adjoint step kernel then runs from the segment's last step to its first,
-// carrying mu = the adjoint of the pre-collision state in a ping-pong pair
-// (one or K steps per launch), and each of its launches also carries as
-// many recompute steps of the next-older segment into the other buffer
-// (independent work, so the small launches fill the chip).  A captured
+// Backward: segments of C steps, newest first.  Each segment is recomputed
+// from its checkpoint, and the recompute keeps of every step only what the
+// adjoint linearises about: the u, v and theta planes of the pre-collision
+// state (3 words per node instead of the 14 of a state), in one of two
+// segment buffers; the adjoint step kernel then runs from the segment's
+// last step to its first, carrying mu = the adjoint of the pre-collision
+// state in a ping-pong pair (one or K steps per launch), and each of its
+// launches also carries as many recompute steps of the next-older segment
+// into the other buffer (independent work, so the small launches fill the
+// chip).  A captured
 // graph of one full segment is replayed for every full segment; the
 // segment's first step index is read from device memory, updated before
 // each replay.
@@ -37,9 +40,13 @@ namespace dmrt {
 struct AdjointState {
     long N = 0, K = 0, C = 0;
     int nseg = 0;
-    size_t slot_elems = 0;       // 14 planes
+    size_t slot_elems = 0;       // 14 planes (a state)
+    size_t lp_elems = 0;         // 3 planes (a linearisation point)
     void* ckpt = nullptr;        // nseg slots: s(k C)
-    void* seg[2] = {nullptr, nullptr};   // two buffers of C slots: s(k C + j)
+    // two buffers of C linearisation points: slot j - 1 holds u, v, theta
+    // of the pre-collision state of step k C + j
+    void* seg[2] = {nullptr, nullptr};
+    void* rst = nullptr;         // 2 states: the recompute's running state
     void* lam = nullptr;         // 2 slots of mu
     double* nu_acc = nullptr;    // n
     double* gthw = nullptr;      // n
@@ -75,7 +82,7 @@ void free_adjoint(AdjointState* a)
             if (a->bwd_def[p][b]) (void)hipGraphDestroy(a->bwd_def[p][b]);
         }
     }
-    void* ptrs[] = {a->ckpt, a->seg[0], a->seg[1], a->lam, a->nu_acc, a->gthw, a->grad0, a->sum,
+    void* ptrs[] = {a->ckpt, a->seg[0], a->seg[1], a->rst, a->lam, a->nu_acc, a->gthw, a->grad0, a->sum,
                     a->n0, a->n0_table};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -204,7 +211,7 @@ AdjArgs<real> adj_args(const dmrt_cavity* h, const AdjointState* a)
     A.seed0 = real(-9.0 * c);
     A.seed1 = real(c);
     A.cabb = (4.0 + h->d.a) / 10.0;
-    A.slot = (long)a->slot_elems;
+    A.lslot = (long)a->lp_elems;
     A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
     A.tiles_x = (h->n + h->block_x - 1) / h->block_x;
     A.tiles = A.tiles_x * ((h->n + h->block_y - 1) / h->block_y);
@@ -228,7 +235,6 @@ int launch_adjk(const dmrt_cavity* h, hipStream_t s, const AdjArgs<real>* A, con
 {
     const int K = h->adj_temporal, R = h->adj_rows;
     const dim3 block(kFootW, R);
-    const long slot = A ? A->slot : (long)h->adj->slot_elems;
     auto padded = [](int t) { return (t + 7) / 8 * 8; };
 #define DMRT_AKR(KK, RR)                                                                               \
     if (K == KK && R == RR) {                                                                           \
@@ -239,8 +245,8 @@ int launch_adjk(const dmrt_cavity* h, hipStream_t s, const AdjArgs<real>* A, con
             hipLaunchKernelGGL((adjk_kernel<real, RR, KK>),                                             \
                                dim3(A->xcd_remap ? padded(A->tiles) : A->tiles), block, 0, s, *A);      \
         else                                                                                            \
-            hipLaunchKernelGGL((stepk_all_kernel<real, RR, KK>),                                        \
-                               dim3(F->xcd_remap ? padded(F->tiles) : F->tiles), block, 0, s, *F, slot); \
+            hipLaunchKernelGGL((stepk_rec_kernel<real, RR, KK>),                                        \
+                               dim3(F->xcd_remap ? padded(F->tiles) : F->tiles), block, 0, s, *F);       \
         return record_hip(hipGetLastError(), "adjoint K-step kernel");                                 \
     }
     DMRT_FOR_EACH_KR(DMRT_AKR)
@@ -248,20 +254,21 @@ int launch_adjk(const dmrt_cavity* h, hipStream_t s, const AdjArgs<real>* A, con
     return DMRT_EINVAL;
 }
 
-// Backward of one segment held in buffer `b` (len states), pipelined with
-// the recompute of the next-older segment into buffer b ^ 1 (rec_len
-// states, slot 0 already filled; 0 when there is none).  Adjoint launches
-// run from the segment's newest step down, K = h->adj_temporal steps each
-// while at least K remain, then single steps; recompute launches fill slots
-// 1, 2, ... of the other buffer the same way.  The i-th adjoint launch and
-// the i-th recompute launch share one kernel when they take the same number
-// of steps.  *flips receives the number of adjoint launches (mu copy
-// changes).
+// Backward of one segment whose linearisation points are in buffer `b`
+// (len steps), pipelined with the recompute of the next-older segment
+// (rec_len steps, its checkpoint already in running-state slot 0; 0 when
+// there is none), whose points go to buffer b ^ 1.  Adjoint launches run
+// from the segment's newest step down, K = h->adj_temporal steps each while
+// at least K remain, then single steps; recompute launches take steps
+// 1, 2, ... the same way, alternating between the two running states.  The
+// i-th adjoint launch and the i-th recompute launch share one kernel when
+// they take the same number of steps.  *flips receives the number of
+// adjoint launches (mu copy changes).
 template <typename real>
 int enqueue_segment(dmrt_cavity* h, AdjointState* a, hipStream_t s, int b, long len, long rec_len,
                     int lam_from, int* flips)
 {
-    const size_t se = a->slot_elems, P = h->plane;
+    const size_t se = a->slot_elems, le = a->lp_elems, P = h->plane;
     const int K = h->adj_temporal, R = h->adj_rows;
     const AdjArgs<real> A1 = adj_args<real>(h, a);
     AdjArgs<real> AK = A1;
@@ -269,26 +276,26 @@ int enqueue_segment(dmrt_cavity* h, AdjointState* a, hipStream_t s, int b, long 
         k_geometry(h->n, K, R, AK.tiles_x, AK.tiles);
         AK.xcd_remap = h->xcd_remap;
     }
-    int l = lam_from, nl = 0;
-    long j = len;      // the next adjoint launch forms mu(n0 + j) from slot j - 1
-    long r = 1;        // the next recompute slot
-    while (j >= 1 || r < rec_len) {
+    int l = lam_from, nl = 0, rp = 0;
+    long j = len;      // the next adjoint launch forms mu(n0 + j) at the point in slot j - 1
+    long r = 1;        // the next recompute step (its point goes to slot r - 1)
+    while (j >= 1 || r <= rec_len) {
         const int ka = j < 1 ? 0 : (K >= 2 && j >= K ? K : 1);
-        const int kr = r >= rec_len ? 0 : (K >= 2 && r + K - 1 <= rec_len - 1 ? K : 1);
+        const int kr = r > rec_len ? 0 : (K >= 2 && r + K - 1 <= rec_len ? K : 1);
         AdjArgs<real> A = ka >= 2 ? AK : A1;
         if (ka) {
-            real* st = slot<real>(a->seg[b], se, j - 1);
-            A.fs = st;
-            A.gs = st + 9 * P;
+            A.lp = slot<real>(a->seg[b], le, j - 1);
             A.lin = slot<real>(a->lam, se, l);
             A.lout = slot<real>(a->lam, se, l ^ 1);
             A.j = (int)j;
         }
         StepArgs<real> F{};
         if (kr) {
-            real* src = slot<real>(a->seg[b ^ 1], se, r - 1);
-            real* dst = slot<real>(a->seg[b ^ 1], se, r);
+            real* src = slot<real>(a->rst, se, rp);
+            real* dst = slot<real>(a->rst, se, rp ^ 1);
             F = step_args<real>(h, src, src + 9 * P, dst, dst + 9 * P);
+            F.lp = slot<real>(a->seg[b ^ 1], le, r - 1);
+            F.lslot = (long)le;
             if (kr >= 2) k_geometry(h->n, K, R, F.tiles_x, F.tiles);
         }
         int rc = DMRT_OK;
@@ -308,18 +315,23 @@ int enqueue_segment(dmrt_cavity* h, AdjointState* a, hipStream_t s, int b, long 
                                    s, A);
                 rc = record_hip(hipGetLastError(), "adj_step_kernel");
             }
-            if (!rc && kr >= 2) rc = launch_adjk<real>(h, s, nullptr, &F);
-            else if (!rc && kr == 1) rc = launch_fwd<real>(h, a, s, F.fin, F.gin, F.fout, F.gout, false);
+            if (!rc && kr >= 2) {
+                rc = launch_adjk<real>(h, s, nullptr, &F);
+            } else if (!rc && kr == 1) {
+                const int nb = h->xcd_remap ? (F.tiles + 7) / 8 * 8 : F.tiles;
+                hipLaunchKernelGGL((rec_step_kernel<real>), dim3(nb), dim3(h->block_x, h->block_y), 0, s, F);
+                rc = record_hip(hipGetLastError(), "rec_step_kernel");
+            }
         }
         if (rc) return rc;
         if (ka) { j -= ka; l ^= 1; ++nl; }
-        r += kr;
+        if (kr) { r += kr; rp ^= 1; }
     }
     if (flips) *flips = nl;
     return DMRT_OK;
 }
 
-// Recompute of slots [1, len) of buffer b on its own (the newest segment).
+// Recompute of the newest segment on its own (its points go to buffer b).
 template <typename real>
 int enqueue_recompute(dmrt_cavity* h, AdjointState* a, hipStream_t s, int b, long len)
 {
@@ -337,11 +349,13 @@ int ensure_state(dmrt_cavity* h, long N, long K, long C)
     h->adj = a;
     a->N = N; a->K = K; a->C = C; a->nseg = nseg;
     a->slot_elems = 14 * (size_t)h->plane;
-    const size_t sb = a->slot_elems * h->esz;
+    a->lp_elems = 3 * (size_t)h->plane;
+    const size_t sb = a->slot_elems * h->esz, lb = a->lp_elems * h->esz;
     const size_t nn = (size_t)h->n * h->n;
     HIPCHK(hipMalloc(&a->ckpt, sb * nseg));
-    HIPCHK(hipMalloc(&a->seg[0], sb * C));
-    HIPCHK(hipMalloc(&a->seg[1], sb * C));
+    HIPCHK(hipMalloc(&a->seg[0], lb * C));
+    HIPCHK(hipMalloc(&a->seg[1], lb * C));
+    HIPCHK(hipMalloc(&a->rst, sb * 2));
     HIPCHK(hipMalloc(&a->lam, sb * 2));
     HIPCHK(hipMemsetAsync(a->lam, 0, sb * 2, h->stream));
     HIPCHK(hipMalloc(&a->nu_acc, h->n * sizeof(double)));
@@ -411,22 +425,23 @@ int backward_t(dmrt_cavity* h, double* gw, double* g0)
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemsetAsync(a->gthw, 0, h->n * sizeof(double), h->stream));
     auto seg_len = [&](int k) { return std::min<long>(a->C, a->N - (long)k * a->C); };
-    auto load_ckpt = [&](int k, int b) -> int {
-        HIPCHK(hipMemcpyAsync(a->seg[b], static_cast<char*>(a->ckpt) + (size_t)k * se * esz, se * esz,
+    // checkpoint k into the recompute's running-state slot 0
+    auto load_ckpt = [&](int k) -> int {
+        HIPCHK(hipMemcpyAsync(a->rst, static_cast<char*>(a->ckpt) + (size_t)k * se * esz, se * esz,
                               hipMemcpyDeviceToDevice, h->stream));
         return DMRT_OK;
     };
     // prologue: the newest segment is recomputed on its own
     const int last = a->nseg - 1;
     int rc;
-    if ((rc = load_ckpt(last, last & 1))) return rc;
+    if ((rc = load_ckpt(last))) return rc;
     if ((rc = enqueue_recompute<real>(h, a, h->stream, last & 1, seg_len(last)))) return rc;
     int l = 0;
     for (int k = last; k >= 0; --k) {
         const int b = k & 1;
         const long len = seg_len(k);
         const long rec_len = k >= 1 ? seg_len(k - 1) : 0;
-        if (k >= 1 && (rc = load_ckpt(k - 1, b ^ 1))) return rc;
+        if (k >= 1 && (rc = load_ckpt(k - 1))) return rc;
         HIPCHK(hipMemcpyAsync(a->n0, a->n0_table + k, sizeof(int), hipMemcpyDeviceToDevice, h->stream));
         if (len == a->C && rec_len == a->C && a->C >= 2) {
             // every full segment with a full predecessor has the same launch

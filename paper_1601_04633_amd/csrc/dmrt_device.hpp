@@ -192,6 +192,10 @@ struct StepArgs {
     // samp[(j - 1) * 2 n + 2 y + x] (FP64, summed as the Nusselt kernel sums)
     double* __restrict__ samp = nullptr;
     int samp_mask = 0;
+    // adjoint recompute: the linearisation point (u, v, theta planes) of
+    // every step, step t + j at lp + (j - 1) lslot
+    real* __restrict__ lp = nullptr;
+    long lslot = 0;
 };
 
 // Temperature sum of a node's post-collision g in FP64, in the order the
@@ -371,15 +375,17 @@ __global__ void __launch_bounds__(1024) step_nu_kernel(StepArgs<real> A, const d
 // to the populations as lf += M^T (Ldrho, Lu, Lv, Lm3, ..., Lm8) (the
 // forward reconstruction, here with density and momentum terms), likewise
 // lg += N^T (...) + Ltheta for D2Q5.
+//
+// The Jacobian depends on the pre-collision state only through its velocity
+// (u, v) and temperature theta (the relaxation and the moment transforms
+// are linear, the equilibria of Eq. 34 and Eq. 42 and the force image of
+// Eq. 26 are functions of u, v, theta), so collide_vjp_at takes just those
+// three values: the forward step's own u, v, theta, bitwise.
 template <typename real>
-__host__ __device__ __forceinline__ void collide_vjp(const real (&f)[9], const real (&g)[5], const Coef<real>& c,
-                                            real (&lf)[9], real (&lg)[5])
+__host__ __device__ __forceinline__ void collide_vjp_at(real u, real v, real theta, const Coef<real>& c,
+                                                        real (&lf)[9], real (&lg)[5])
 {
     const real two = real(2), four = real(4);
-    // forward quantities at the pre-collision state, as in collide()
-    const real d13 = f[1] - f[3], d24 = f[2] - f[4], d57 = f[5] - f[7], d86 = f[8] - f[6];
-    const real u = d13 + (d57 + d86), v = d24 + (d57 - d86);
-    const real theta = g[0] + ((g[1] + g[3]) + (g[2] + g[4]));
     const real uu = u * u, vv = v * v, uv = u * v;
     const real q2 = uu + vv, e4 = uu - vv;
     const real Gy = fmr(c.gbeta, theta, c.gy0);
@@ -455,10 +461,24 @@ __host__ __device__ __forceinline__ void collide_vjp(const real (&f)[9], const r
     lg[4] += t34m - Ln2;
 }
 
+// The same at the pre-collision state (f, g), with u, v, theta formed as
+// collide() forms them.
+template <typename real>
+__host__ __device__ __forceinline__ void collide_vjp(const real (&f)[9], const real (&g)[5], const Coef<real>& c,
+                                            real (&lf)[9], real (&lg)[5])
+{
+    const real d13 = f[1] - f[3], d24 = f[2] - f[4], d57 = f[5] - f[7], d86 = f[8] - f[6];
+    const real u = d13 + (d57 + d86), v = d24 + (d57 - d86);
+    const real theta = g[0] + ((g[1] + g[3]) + (g[2] + g[4]));
+    collide_vjp_at<real>(u, v, theta, c, lf, lg);
+}
+
 template <typename real>
 struct AdjArgs {
-    const real* __restrict__ fs;     // s(m-1): f planes (segment slot j - 1)
-    const real* __restrict__ gs;     // s(m-1): g planes
+    // linearisation point of step m (segment slot j - 1): the u, v and
+    // theta planes of the pre-collision state p(m), as the forward step
+    // computed them
+    const real* __restrict__ lp;
     const real* __restrict__ lin;    // mu(m+1): 14 planes (f then g)
     real* __restrict__ lout;         // mu(m), or mu(m-K+1) for K steps per launch
     const real* __restrict__ thw;
@@ -468,7 +488,7 @@ struct AdjArgs {
     int win_start;                   // first step of the objective window
     real seed0, seed1;               // dJ/dg*_i(m) at x = 0 and x = 1 for m in the window
     double cabb;                     // Eq. 45 constant in FP64
-    long slot;                       // elements between consecutive segment slots
+    long lslot;                      // elements between consecutive segment slots (3 planes)
     int n, pitch, plane, tiles_x, tiles;
     int xcd_remap;
     Coef<real> c;
@@ -505,30 +525,22 @@ __device__ __forceinline__ void adj_pull(const real* __restrict__ mu, int n, int
     lf[7] = ldb(mu, (hxm && hym) ? kb + 7 * Pb - rb - E : kb + 5 * Pb);
     lf[8] = ldb(mu, (hxp && hym) ? kb + 8 * Pb - rb + E : kb + 6 * Pb);
     const real* __restrict__ mg = mu + 9 * P;
+    // one load per link (the address selected), so no load sits in a branch
+    const real m1 = ldb(mg, hxp ? kb + Pb + E : kb + 3 * Pb);
+    const real m3 = ldb(mg, hxm ? kb + 3 * Pb - E : kb + Pb);
     lg[0] = ldb(mg, kb) + sd;
-    lg[1] = hxp ? ldb(mg, kb + Pb + E) + sd : sd - ldb(mg, kb + 3 * Pb);           // Eq. 45, right wall
+    lg[1] = hxp ? m1 + sd : sd - m1;                                               // Eq. 45, right wall
     lg[2] = ldb(mg, hyp ? kb + 2 * Pb + rb : kb + 4 * Pb) + sd;                    // Eq. 44
-    lg[3] = hxm ? ldb(mg, kb + 3 * Pb - E) + sd : sd - ldb(mg, kb + Pb);           // Eq. 45, left wall
+    lg[3] = hxm ? m3 + sd : sd - m3;                                               // Eq. 45, left wall
     lg[4] = ldb(mg, hym ? kb + 4 * Pb - rb : kb + 2 * Pb) + sd;
 }
 
-// One adjoint node update: mu(m) = C'(p(m))^T lambda(m), with p(m) gathered
-// from s(m-1) exactly as in the forward step.  The derivative of the
-// anti-bounce-back constant feeds dJ/dtheta_w at the hot wall.
-template <typename real>
-__device__ __forceinline__ void adj_node(const real* __restrict__ fs, const real* __restrict__ gs,
-                                         const AdjArgs<real>& A, int x, int y, real (&lf)[9],
-                                         real (&lg)[5])
-{
-    real f[9], g[5];
-    gather<real, BC_CAVITY>(fs, gs, A.thw, A.n, A.pitch, A.plane, x, y, A.c, f, g);
-    collide_vjp<real>(f, g, A.c, lf, lg);
-}
-
 // Adjoint of step m for the cavity: lambda(m) = S^T mu(m+1) + dJ/ds(m),
-// mu(m) = C'(p(m))^T lambda(m); the segment's slot j - 1 holds s(m-1).
-// Storing mu rather than lambda makes the transposed streaming a pull, so
-// every thread writes only its own node.
+// mu(m) = C'(p(m))^T lambda(m), the Jacobian taken at the linearisation
+// point of step m (segment slot j - 1).  Storing mu rather than lambda
+// makes the transposed streaming a pull, so every thread writes only its
+// own node.  The derivative of the anti-bounce-back constant feeds
+// dJ/dtheta_w at the hot wall.
 template <typename real>
 __device__ __forceinline__ void adj_tile(const AdjArgs<real>& A, int tile)
 {
@@ -538,18 +550,28 @@ __device__ __forceinline__ void adj_tile(const AdjArgs<real>& A, int tile)
     const int y = ty * blockDim.y + threadIdx.y;
     const int n = A.n;
     if (x >= n || y >= n) return;
-    const int P = A.plane;
+    const int P = A.plane, k = y * A.pitch + x;
     const int m = *A.n0p + A.j;
     real lf[9], lg[5];
     adj_pull<real>(A.lin, n, A.pitch, P, x, y, adj_seed_at<real>(x, m >= A.win_start, A.seed0, A.seed1),
                    lf, lg);
-    adj_node<real>(A.fs, A.gs, A, x, y, lf, lg);
-    const unsigned kb = unsigned(y * A.pitch + x) * sizeof(real), Pb = unsigned(P) * sizeof(real);
+    collide_vjp_at<real>(A.lp[k], A.lp[P + k], A.lp[2 * P + k], A.c, lf, lg);
+    const unsigned kb = unsigned(k) * sizeof(real), Pb = unsigned(P) * sizeof(real);
 #pragma unroll
     for (int i = 0; i < 9; ++i) stb(A.lout, kb + i * Pb, lf[i]);
 #pragma unroll
     for (int i = 0; i < 5; ++i) stb(A.lout, kb + (9 + i) * Pb, lg[i]);
     if (x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
+}
+
+// Linearisation point of a node: the u, v, theta of its pre-collision
+// state (collide's outputs) into the three planes at lp.
+template <typename real>
+__device__ __forceinline__ void store_lp(real* __restrict__ lp, int P, int k, real u, real v, real theta)
+{
+    lp[k] = u;
+    lp[P + k] = v;
+    lp[2 * P + k] = theta;
 }
 
 template <typename real>
@@ -559,10 +581,40 @@ __global__ void __launch_bounds__(1024) adj_step_kernel(AdjArgs<real> A)
     adj_tile<real>(A, blockIdx.x);
 }
 
+// One forward step of the recompute: gather, collide, store the state and
+// the node's linearisation point (R.lp).
+template <typename real>
+__device__ __forceinline__ void rec_node(const StepArgs<real>& R, int x, int y)
+{
+    real f[9], g[5];
+    gather<real, BC_CAVITY>(R.fin, R.gin, R.thw, R.n, R.pitch, R.plane, x, y, R.c, f, g);
+    real th, ux, uy;
+    collide<real>(f, g, R.c, th, ux, uy);
+    const int k = y * R.pitch + x, P = R.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R.fout[i * P + k] = f[i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) R.gout[i * P + k] = g[i];
+    store_lp<real>(R.lp, P, k, ux, uy, th);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(1024) rec_step_kernel(StepArgs<real> R)
+{
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, R.xcd_remap);
+    if (tile >= R.tiles) return;
+    const int ty = tile / R.tiles_x;
+    const int tx = tile - ty * R.tiles_x;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y = ty * blockDim.y + threadIdx.y;
+    if (x >= R.n || y >= R.n) return;
+    rec_node<real>(R, x, y);
+}
+
 // One adjoint step of the current segment and, in the same launch, one
 // forward step recomputing the next (older) segment: the two touch disjoint
 // buffers.  Workgroups [0, A.tiles) take adjoint tiles, the rest take
-// forward tiles of R.
+// recompute tiles of R.
 template <typename real>
 __global__ void __launch_bounds__(1024) adj_fused_kernel(AdjArgs<real> A, StepArgs<real> R)
 {
@@ -578,7 +630,7 @@ __global__ void __launch_bounds__(1024) adj_fused_kernel(AdjArgs<real> A, StepAr
     const int x = tx * blockDim.x + threadIdx.x;
     const int y = ty * blockDim.y + threadIdx.y;
     if (x >= R.n || y >= R.n) return;
-    node_update<real, BC_CAVITY>(R.fin, R.gin, R.fout, R.gout, R.thw, R.n, R.pitch, R.plane, x, y, R.c);
+    rec_node<real>(R, x, y);
 }
 
 // mu(N+1) = 0: the first adjoint step then forms lambda(N) = dJ/ds(N).
@@ -725,17 +777,18 @@ __device__ __forceinline__ void lds_last_phase(const real* lds, real* __restrict
 // (R - 2(K-1)) nodes; phase j computes step t + j on the footprint shrunk by
 // j - 1 nodes on each side (phase 1 from HBM, the others from LDS; the
 // intermediate phases hold their result in registers across a barrier and
-// then overwrite the LDS copy), and the last phase stores to HBM.  With ALL,
-// every intermediate state is also stored on the output tile (a partition
-// of the domain), state t + j at fout/gout + (j - 1) * slot: the adjoint's
-// recompute keeps every state of a segment.
+// then overwrite the LDS copy), and the last phase stores to HBM.  With REC
+// (the adjoint's recompute), every phase also stores the linearisation
+// point (u, v, theta) of its step on the output tile (a partition of the
+// domain), step t + j at A.lp + (j - 1) A.lslot.
 // With NU, every step of the launch also adds its hot-wall Nusselt sum
 // 8 theta_w - 9 theta(0, y) + theta(1, y) (Eqs. 18-19) to acc[y], in FP64
 // and in the same order and arithmetic as step_nu_kernel; the x = 0 and
-// x = 1 nodes are neighbouring lanes of one wavefront.
+// x = 1 nodes are neighbouring lanes of one wavefront.  The owning lane
+// keeps acc[y] in a register for the whole launch (read at the start,
+// written at the end), so no phase waits on a global read.
 template <typename real>
-__device__ __forceinline__ void nu_row_add(const real (&g)[5], bool have, bool wall_lane, int y,
-                                           const double* __restrict__ thw_d, double* __restrict__ acc)
+__device__ __forceinline__ void nu_row_add(const real (&g)[5], bool have, bool wall_lane, double tw, double& acc)
 {
     double ts = 0.0;
     if (have) {
@@ -743,11 +796,11 @@ __device__ __forceinline__ void nu_row_add(const real (&g)[5], bool have, bool w
         for (int i = 0; i < 5; ++i) ts += double(g[i]);
     }
     const double ts1 = __shfl_down(ts, 1, 64);
-    if (wall_lane) acc[y] += 8.0 * thw_d[y] - 9.0 * ts + ts1;
+    if (wall_lane) acc += 8.0 * tw - 9.0 * ts + ts1;
 }
 
-template <typename real, int R, int K, bool ALL, bool NU = false>
-__device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, int tile, long slot,
+template <typename real, int R, int K, bool REC, bool NU = false>
+__device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, int tile,
                                            const double* __restrict__ thw_d = nullptr,
                                            double* __restrict__ acc = nullptr)
 {
@@ -761,6 +814,12 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
     const int n = A.n, P = A.plane, k = y * A.pitch + x;
     const bool inside = x >= 0 && x < n && y >= 0 && y < n;
     const bool own = inside && lx >= K - 1 && lx <= kFootW - K && ly >= K - 1 && ly <= R - K;
+    const bool nown = NU && own && x == 0;
+    double nacc = 0.0, ntw = 0.0;
+    if (nown) {
+        nacc = acc[y];
+        ntw = thw_d[y];
+    }
     real f[9], g[5];
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = real(0);
@@ -774,40 +833,28 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
         for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = f[i];
 #pragma unroll
         for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kFootW + lx] = g[i];
-        if (ALL && own) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) A.fout[i * P + k] = f[i];
-#pragma unroll
-            for (int i = 0; i < 5; ++i) A.gout[i * P + k] = g[i];
-        }
-        if (!ALL && !NU && (A.samp_mask & 2) && own) samp_put<real>(A, 1, x, y, g);
+        if (REC && own) store_lp<real>(A.lp, P, k, ux, uy, th);
+        if (!REC && !NU && (A.samp_mask & 2) && own) samp_put<real>(A, 1, x, y, g);
     }
-    if constexpr (NU) nu_row_add<real>(g, inside, own && x == 0, y, thw_d, acc);
+    if constexpr (NU) nu_row_add<real>(g, inside, nown, ntw, nacc);
     __syncthreads();
 #pragma unroll
     for (int j = 2; j < K; ++j) {
         const bool act = inside && lx >= j - 1 && lx <= kFootW - j && ly >= j - 1 && ly <= R - j;
+        real lth = real(0), lux = real(0), luy = real(0);
         if (act) {
             gather_lds<real, R>(lds, A.thw, n, x, y, lx, ly, A.c, f, g);
-            real th, ux, uy;
-            collide<real>(f, g, A.c, th, ux, uy);
+            collide<real>(f, g, A.c, lth, lux, luy);
         }
-        if constexpr (NU) nu_row_add<real>(g, act, own && x == 0, y, thw_d, acc);
+        if constexpr (NU) nu_row_add<real>(g, act, nown, ntw, nacc);
         __syncthreads();
         if (act) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = f[i];
 #pragma unroll
             for (int i = 0; i < 5; ++i) lds[((9 + i) * R + ly) * kFootW + lx] = g[i];
-            if (ALL && own) {
-                real* fo = A.fout + (j - 1) * slot;
-                real* go = A.gout + (j - 1) * slot;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) fo[i * P + k] = f[i];
-#pragma unroll
-                for (int i = 0; i < 5; ++i) go[i * P + k] = g[i];
-            }
-            if (!ALL && !NU && (A.samp_mask & (1 << j)) && own) samp_put<real>(A, j, x, y, g);
+            if (REC && own) store_lp<real>(A.lp + (j - 1) * A.lslot, P, k, lux, luy, lth);
+            if (!REC && !NU && (A.samp_mask & (1 << j)) && own) samp_put<real>(A, j, x, y, g);
         }
         __syncthreads();
     }
@@ -823,12 +870,24 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
 #pragma unroll
             for (int i = 0; i < 5; ++i) stb(A.gout, kb + i * Pb, g[i]);
         }
-        nu_row_add<real>(g, own, own && x == 0, y, thw_d, acc);
+        nu_row_add<real>(g, own, nown, ntw, nacc);
+        if (nown) acc[y] = nacc;
         return;
     }
     if (!own) return;
-    const long last = ALL ? (K - 1) * slot : 0;
-    lds_last_phase<real, R>(lds, A.fout + last, A.gout + last, A.thw, n, A.pitch, P, x, y, lx, ly, A.c);
+    if constexpr (REC) {
+        gather_lds<real, R>(lds, A.thw, n, x, y, lx, ly, A.c, f, g);
+        real th, ux, uy;
+        collide<real>(f, g, A.c, th, ux, uy);
+        const unsigned kb = unsigned(k) * sizeof(real), Pb = unsigned(P) * sizeof(real);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) stb(A.fout, kb + i * Pb, f[i]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) stb(A.gout, kb + i * Pb, g[i]);
+        store_lp<real>(A.lp + (K - 1) * A.lslot, P, k, ux, uy, th);
+        return;
+    }
+    lds_last_phase<real, R>(lds, A.fout, A.gout, A.thw, n, A.pitch, P, x, y, lx, ly, A.c);
 }
 
 template <typename real, int R, int K>
@@ -837,7 +896,7 @@ __global__ void __launch_bounds__(kFootW * R) stepk_kernel(StepArgs<real> A)
     __shared__ real lds[14 * R * kFootW];
     const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
     if (tile >= A.tiles) return;                      // uniform per workgroup
-    stepk_tile<real, R, K, false>(A, lds, tile, 0);
+    stepk_tile<real, R, K, false>(A, lds, tile);
 }
 
 // K steps per launch that also accumulate the hot-wall Nusselt sums
@@ -849,17 +908,17 @@ __global__ void __launch_bounds__(kFootW * R) stepk_nu_kernel(StepArgs<real> A, 
     __shared__ real lds[14 * R * kFootW];
     const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
     if (tile >= A.tiles) return;
-    stepk_tile<real, R, K, false, true>(A, lds, tile, 0, thw_d, acc);
+    stepk_tile<real, R, K, false, true>(A, lds, tile, thw_d, acc);
 }
 
 // K forward steps storing every state (the adjoint's recompute on its own).
 template <typename real, int R, int K>
-__global__ void __launch_bounds__(kFootW * R) stepk_all_kernel(StepArgs<real> A, long slot)
+__global__ void __launch_bounds__(kFootW * R) stepk_rec_kernel(StepArgs<real> A)
 {
     __shared__ real lds[14 * R * kFootW];
     const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
     if (tile >= A.tiles) return;
-    stepk_tile<real, R, K, true>(A, lds, tile, slot);
+    stepk_tile<real, R, K, true>(A, lds, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -1119,9 +1178,9 @@ __device__ __forceinline__ void adj_pull_lds(const real* lds, int n, int x, int 
 // K adjoint steps per launch (m = *n0p + j down to m - K + 1): the mirror
 // image of stepk_tile.  Phase 1 pulls mu(m+1) from HBM on the footprint and
 // forms mu(m) into LDS; phase i pulls mu(m-i+2) from LDS on the footprint
-// shrunk by i - 1 nodes per side and forms mu(m-i+1), the state s(m-i)
-// coming from segment slot j - i (HBM); the last phase stores mu(m-K+1) on
-// the output tile.  Only output-tile nodes add to dJ/dtheta_w, in the same
+// shrunk by i - 1 nodes per side and forms mu(m-i+1), linearised at the
+// point stored in segment slot j - i (HBM); the last phase stores mu(m-K+1)
+// on the output tile.  Only output-tile nodes add to dJ/dtheta_w, in the same
 // order as single steps, so the result equals K single-step launches.
 template <typename real, int R, int K>
 __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int tile)
@@ -1130,34 +1189,41 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
     static_assert(W > 0 && HO > 0, "tile too small for K steps");
     const int tyt = tile / A.tiles_x;
     const int txt = tile - tyt * A.tiles_x;
-    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int lx = threadIdx.x;
+    const int ly = __builtin_amdgcn_readfirstlane(threadIdx.y);   // blockDim.x = 64: one row per wave
     const int x = txt * W - (K - 1) + lx;
     const int y = tyt * HO - (K - 1) + ly;
     const int n = A.n, P = A.plane;
     const bool inside = x >= 0 && x < n && y >= 0 && y < n;
     const bool own = inside && lx >= K - 1 && lx <= kFootW - K && ly >= K - 1 && ly <= R - K;
-    const int m = *A.n0p + A.j;
+    // dJ/dtheta_w of row y: the owning lane at x = 0 keeps it in a register
+    // for the whole launch (same fma sequence as single steps)
+    const bool gown = own && x == 0;
+    double gacc = 0.0;
+    if (gown) gacc = A.gthw[y];
+    // the segment's first step index through the constant address space (a
+    // scalar load that does not wait for the vector loads in flight)
+    const int m = ((const __attribute__((address_space(4))) int*)A.n0p)[0] + A.j;
+    // every global read below is unconditional, at the node clamped into
+    // the cavity (values of lanes outside are never used), so no read sits
+    // in a branch and the reads of the next phase stay in flight while the
+    // current one computes
+    const int xc = min(max(x, 0), n - 1), yc = min(max(y, 0), n - 1);
+    const int kc = yc * A.pitch + xc;
     real lf[9], lg[5];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) lf[i] = real(0);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) lg[i] = real(0);
-    // the forward state each phase linearises about does not depend on mu:
-    // the gather for phase j + 1 is issued before the work of phase j, so
-    // one gather is always in flight (registers sf, sg hold the next one)
-    real cf[9], cg[5], sf[9], sg[5];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) { cf[i] = real(0); sf[i] = real(0); }
-#pragma unroll
-    for (int i = 0; i < 5; ++i) { cg[i] = real(0); sg[i] = real(0); }
-    if (inside) gather<real, BC_CAVITY>(A.fs, A.gs, A.thw, n, A.pitch, P, x, y, A.c, cf, cg);
-    if (K >= 2 && inside && lx >= 1 && lx <= kFootW - 2 && ly >= 1 && ly <= R - 2)
-        gather<real, BC_CAVITY>(A.fs - A.slot, A.gs - A.slot, A.thw, n, A.pitch, P, x, y, A.c, sf, sg);
+    // linearisation points: this phase's (cu, cv, ct) and the next one's
+    // (su, sv, st), one read of each plane at the node itself
+    real cu = A.lp[kc], cv = A.lp[P + kc], ct = A.lp[2 * P + kc];
+    real su = real(0), sv = real(0), st = real(0);
+    adj_pull<real>(A.lin, n, A.pitch, P, xc, yc, adj_seed_at<real>(x, m >= A.win_start, A.seed0, A.seed1),
+                   lf, lg);
+    if (K >= 2) {
+        const real* q = A.lp - A.lslot;
+        su = q[kc]; sv = q[P + kc]; st = q[2 * P + kc];
+    }
     if (inside) {
-        adj_pull<real>(A.lin, n, A.pitch, P, x, y, adj_seed_at<real>(x, m >= A.win_start, A.seed0, A.seed1),
-                       lf, lg);
-        collide_vjp<real>(cf, cg, A.c, lf, lg);
-        if (own && x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
+        collide_vjp_at<real>(cu, cv, ct, A.c, lf, lg);
+        if (gown) gacc = __builtin_fma(A.cabb, double(lg[1]), gacc);
 #pragma unroll
         for (int i = 0; i < 9; ++i) lds[(i * R + ly) * kFootW + lx] = lf[i];
 #pragma unroll
@@ -1167,19 +1233,17 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
 #pragma unroll
     for (int j = 2; j <= K; ++j) {
         const bool act = inside && lx >= j - 1 && lx <= kFootW - j && ly >= j - 1 && ly <= R - j;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) cf[i] = sf[i];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) cg[i] = sg[i];
-        if (j < K && inside && lx >= j && lx <= kFootW - j - 1 && ly >= j && ly <= R - j - 1)
-            gather<real, BC_CAVITY>(A.fs - j * A.slot, A.gs - j * A.slot, A.thw, n, A.pitch, P, x, y, A.c,
-                                    sf, sg);
+        cu = su; cv = sv; ct = st;
+        if (j < K) {
+            const real* q = A.lp - j * A.lslot;
+            su = q[kc]; sv = q[P + kc]; st = q[2 * P + kc];
+        }
         if (act) {
             const int mj = m - j + 1;
             adj_pull_lds<real, R>(lds, n, x, y, lx, ly,
                                   adj_seed_at<real>(x, mj >= A.win_start, A.seed0, A.seed1), lf, lg);
-            collide_vjp<real>(cf, cg, A.c, lf, lg);
-            if (own && x == 0) A.gthw[y] = __builtin_fma(A.cabb, double(lg[1]), A.gthw[y]);
+            collide_vjp_at<real>(cu, cv, ct, A.c, lf, lg);
+            if (gown) gacc = __builtin_fma(A.cabb, double(lg[1]), gacc);
         }
         if (j == K) break;
         __syncthreads();
@@ -1192,6 +1256,7 @@ __device__ __forceinline__ void adjk_tile(const AdjArgs<real>& A, real* lds, int
         __syncthreads();
     }
     if (!own) return;
+    if (gown) A.gthw[y] = gacc;
     const unsigned kb = unsigned(y * A.pitch + x) * sizeof(real), Pb = unsigned(P) * sizeof(real);
 #pragma unroll
     for (int i = 0; i < 9; ++i) stb(A.lout, kb + i * Pb, lf[i]);
@@ -1221,7 +1286,7 @@ __global__ void __launch_bounds__(kFootW * R) adjk_fused_kernel(AdjArgs<real> A,
         return;
     }
     if (b - A.tiles >= F.tiles) return;
-    stepk_tile<real, R, K, true>(F, lds, b - A.tiles, A.slot);
+    stepk_tile<real, R, K, true>(F, lds, b - A.tiles);
 }
 
 // ---------------------------------------------------------------------------
