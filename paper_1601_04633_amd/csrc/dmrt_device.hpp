@@ -300,6 +300,51 @@ __device__ __forceinline__ void gather(const real* __restrict__ fi, const real* 
     }
 }
 
+// Wall temperature of row y, uniform per wave: a scalar load through the
+// constant address space, which does not wait for vector memory operations
+// in flight.
+template <typename real>
+__device__ __forceinline__ real thw_row(const real* thw, int y)
+{
+    typedef const __attribute__((address_space(4))) real creal;
+    return ((creal*)thw)[y];
+}
+
+// The cavity gather split in two for prefetching: the loads alone, with
+// selected addresses but no branches (every address in bounds for x, y in
+// [0, n)), and the isothermal-wall formula of Eq. 45 applied to them where
+// the values are used; together they give exactly gather<real, BC_CAVITY>.
+template <typename real>
+__device__ __forceinline__ void gather_cavity_loads(const real* __restrict__ fi, const real* __restrict__ gi,
+                                                    int n, int pitch, int P, int x, int y, real (&f)[9],
+                                                    real (&g)[5])
+{
+    constexpr unsigned E = sizeof(real);
+    const unsigned kb = unsigned(y * pitch + x) * E, Pb = unsigned(P) * E, rb = unsigned(pitch) * E;
+    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
+    f[0] = ldb(fi, kb);
+    f[1] = ldb(fi, hxm ? kb + Pb - E : kb + 3 * Pb);
+    f[2] = ldb(fi, hym ? kb + 2 * Pb - rb : kb + 4 * Pb);
+    f[3] = ldb(fi, hxp ? kb + 3 * Pb + E : kb + Pb);
+    f[4] = ldb(fi, hyp ? kb + 4 * Pb + rb : kb + 2 * Pb);
+    f[5] = ldb(fi, (hxm && hym) ? kb + 5 * Pb - rb - E : kb + 7 * Pb);
+    f[6] = ldb(fi, (hxp && hym) ? kb + 6 * Pb - rb + E : kb + 8 * Pb);
+    f[7] = ldb(fi, (hxp && hyp) ? kb + 7 * Pb + rb + E : kb + 5 * Pb);
+    f[8] = ldb(fi, (hxm && hyp) ? kb + 8 * Pb + rb - E : kb + 6 * Pb);
+    g[0] = ldb(gi, kb);
+    g[1] = ldb(gi, hxm ? kb + Pb - E : kb + 3 * Pb);
+    g[2] = ldb(gi, hym ? kb + 2 * Pb - rb : kb + 4 * Pb);        // Eq. 44
+    g[3] = ldb(gi, hxp ? kb + 3 * Pb + E : kb + Pb);
+    g[4] = ldb(gi, hyp ? kb + 4 * Pb + rb : kb + 2 * Pb);
+}
+
+template <typename real>
+__device__ __forceinline__ void gather_cavity_walls(real thw_y, int n, int x, const Coef<real>& c, real (&g)[5])
+{
+    if (x == 0) g[1] = fmr(c.cabb, thw_y, -g[1]);                // Eq. 45
+    if (x == n - 1) g[3] = c.cold - g[3];
+}
+
 // One node update (Eqs. 25-45): gather from the current copy with the wall
 // rules, collide in registers, store into the other copy.  Returns the
 // node's temperature sum of the stored g* in FP64 (used only by the
@@ -701,14 +746,20 @@ static __global__ void __launch_bounds__(256) sum_kernel(const double* __restric
 constexpr int kFootW = 64;         // footprint width (one wavefront)
 
 // First phase of the K-step update: s(t+1) at footprint node (x, y) into LDS.
+// Every lane reads (at its node clamped into the cavity, y uniform per
+// wave), so no global read sits in a branch; lanes outside the cavity
+// store nothing.
 template <typename real, int R>
 __device__ __forceinline__ void lds_first_phase(real* lds, const real* __restrict__ fi,
                                           const real* __restrict__ gi, const real* __restrict__ thw,
                                           int n, int pitch, int P, int x, int y, int lx, int ly,
-                                          const Coef<real>& c)
+                                          bool inside, const Coef<real>& c)
 {
     real f[9], g[5];
-    gather<real, BC_CAVITY>(fi, gi, thw, n, pitch, P, x, y, c, f, g);
+    const int xc = min(max(x, 0), n - 1), yc = min(max(y, 0), n - 1);
+    gather_cavity_loads<real>(fi, gi, n, pitch, P, xc, yc, f, g);
+    if (!inside) return;
+    gather_cavity_walls<real>(thw_row<real>(thw, yc), n, x, c, g);
     real th, ux, uy;
     collide<real>(f, g, c, th, ux, uy);
 #pragma unroll
@@ -808,7 +859,8 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
     static_assert(W > 0 && HO > 0, "tile too small for K steps");
     const int tyt = tile / A.tiles_x;
     const int txt = tile - tyt * A.tiles_x;
-    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int lx = threadIdx.x;
+    const int ly = __builtin_amdgcn_readfirstlane(threadIdx.y);   // blockDim.x = 64: one row per wave
     const int x = txt * W - (K - 1) + lx;
     const int y = tyt * HO - (K - 1) + ly;
     const int n = A.n, P = A.plane, k = y * A.pitch + x;
@@ -821,12 +873,14 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
         ntw = thw_d[y];
     }
     real f[9], g[5];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = real(0);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) g[i] = real(0);
+    // phase 1 reads at the node clamped into the cavity on every lane (no
+    // global read in a branch); lanes outside compute nothing
+    {
+        const int xc = min(max(x, 0), n - 1), yc = min(max(y, 0), n - 1);
+        gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, P, xc, yc, f, g);
+        if (inside) gather_cavity_walls<real>(thw_row<real>(A.thw, yc), n, x, A.c, g);
+    }
     if (inside) {
-        gather<real, BC_CAVITY>(A.fin, A.gin, A.thw, n, A.pitch, P, x, y, A.c, f, g);
         real th, ux, uy;
         collide<real>(f, g, A.c, th, ux, uy);
 #pragma unroll
@@ -938,16 +992,6 @@ __global__ void __launch_bounds__(kFootW * R) stepk_rec_kernel(StepArgs<real> A)
 // end instead of at each 16-row tile, and the result equals K single-step
 // launches exactly (same gathers, same arithmetic).
 
-// Wall temperature of row y, uniform per wave: a scalar load through the
-// constant address space, which does not wait for vector memory operations
-// in flight.
-template <typename real>
-__device__ __forceinline__ real thw_row(const real* thw, int y)
-{
-    typedef const __attribute__((address_space(4))) real creal;
-    return ((creal*)thw)[y];
-}
-
 // Gather of node (x, y) at lane lx from the previous group's ring (14
 // planes of B + 2 rows of 64) with the cavity's wall rules, rows y - 1, y
 // and y + 1 being at slots sm, s0 and sp: every interior link from constant
@@ -986,41 +1030,6 @@ __device__ __forceinline__ void gather_ring(const real* ring, real thw_y, int n,
         if (!(hxp && hyp)) f[7] = b0[5 * PL];
         if (!(hxm && hyp)) f[8] = b0[6 * PL];
     }
-}
-
-// The cavity gather split in two for prefetching: the loads alone, with
-// selected addresses but no branches (every address in bounds for x, y in
-// [0, n)), and the isothermal-wall formula of Eq. 45 applied to them where
-// the values are used; together they give exactly gather<real, BC_CAVITY>.
-template <typename real>
-__device__ __forceinline__ void gather_cavity_loads(const real* __restrict__ fi, const real* __restrict__ gi,
-                                                    int n, int pitch, int P, int x, int y, real (&f)[9],
-                                                    real (&g)[5])
-{
-    constexpr unsigned E = sizeof(real);
-    const unsigned kb = unsigned(y * pitch + x) * E, Pb = unsigned(P) * E, rb = unsigned(pitch) * E;
-    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
-    f[0] = ldb(fi, kb);
-    f[1] = ldb(fi, hxm ? kb + Pb - E : kb + 3 * Pb);
-    f[2] = ldb(fi, hym ? kb + 2 * Pb - rb : kb + 4 * Pb);
-    f[3] = ldb(fi, hxp ? kb + 3 * Pb + E : kb + Pb);
-    f[4] = ldb(fi, hyp ? kb + 4 * Pb + rb : kb + 2 * Pb);
-    f[5] = ldb(fi, (hxm && hym) ? kb + 5 * Pb - rb - E : kb + 7 * Pb);
-    f[6] = ldb(fi, (hxp && hym) ? kb + 6 * Pb - rb + E : kb + 8 * Pb);
-    f[7] = ldb(fi, (hxp && hyp) ? kb + 7 * Pb + rb + E : kb + 5 * Pb);
-    f[8] = ldb(fi, (hxm && hyp) ? kb + 8 * Pb + rb - E : kb + 6 * Pb);
-    g[0] = ldb(gi, kb);
-    g[1] = ldb(gi, hxm ? kb + Pb - E : kb + 3 * Pb);
-    g[2] = ldb(gi, hym ? kb + 2 * Pb - rb : kb + 4 * Pb);        // Eq. 44
-    g[3] = ldb(gi, hxp ? kb + 3 * Pb + E : kb + Pb);
-    g[4] = ldb(gi, hyp ? kb + 4 * Pb + rb : kb + 2 * Pb);
-}
-
-template <typename real>
-__device__ __forceinline__ void gather_cavity_walls(real thw_y, int n, int x, const Coef<real>& c, real (&g)[5])
-{
-    if (x == 0) g[1] = fmr(c.cabb, thw_y, -g[1]);                // Eq. 45
-    if (x == n - 1) g[3] = c.cold - g[3];
 }
 
 // Per-wave constants of the row-marching kernel.
@@ -1499,15 +1508,16 @@ __global__ void __launch_bounds__(kFootW * R) batch_stepk_kernel(
     int t_end, int cur)
 {
     __shared__ real lds[14 * R * kFootW];
-    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int lx = threadIdx.x;
+    const int ly = __builtin_amdgcn_readfirstlane(threadIdx.y);   // blockDim.x = 64: one row per wave
     for (int t = t_begin + blockIdx.x; t < t_end; t += gridDim.x) {
         const TileRef tr = tiles[t];
         const CavityDev<real>& cv = cavs[tr.cav];
         if (cv.dead) continue;                        // uniform per workgroup
         const int x = tr.x0 + lx, y = tr.y0 + ly, n = cv.n;
         const bool inside = x >= 0 && x < n && y >= 0 && y < n;
-        if (inside)
-            lds_first_phase<real, R>(lds, cv.f[cur], cv.g[cur], cv.thw, n, cv.pitch, cv.plane, x, y, lx, ly, cv.c);
+        lds_first_phase<real, R>(lds, cv.f[cur], cv.g[cur], cv.thw, n, cv.pitch, cv.plane, x, y, lx, ly, inside,
+                                 cv.c);
         __syncthreads();
         real f[9], g[5];
 #pragma unroll
