@@ -236,6 +236,16 @@ __device__ __forceinline__ void stb(real* __restrict__ base, unsigned b, real v)
     *reinterpret_cast<real*>(reinterpret_cast<char*>(base) + b) = v;
 }
 
+// Wall temperature of row y, uniform per wave: a scalar load through the
+// constant address space, which does not wait for vector memory operations
+// in flight.
+template <typename real>
+__device__ __forceinline__ real thw_row(const real* thw, int y)
+{
+    typedef const __attribute__((address_space(4))) real creal;
+    return ((creal*)thw)[y];
+}
+
 // Pull-streaming with the wall rules (Eq. 25, Eqs. 44-45): f_i(r) = f*_i(r - e_i) when
 // r - e_i is inside, else the halfway bounce-back f*_opp(i)(r); for g the
 // same, with Eq. 44 on adiabatic walls and Eq. 45 on the isothermal walls.
@@ -261,8 +271,15 @@ __device__ __forceinline__ void gather(const real* __restrict__ fi, const real* 
         g[0] = ldb(gi, kb);
         g[2] = ldb(gi, hym ? kb + 2 * Pb - rb : kb + 4 * Pb);        // Eq. 44
         g[4] = ldb(gi, hyp ? kb + 4 * Pb + rb : kb + 2 * Pb);
-        g[1] = hxm ? ldb(gi, kb + Pb - E) : fmr(c.cabb, thw[y], -ldb(gi, kb + 3 * Pb));   // Eq. 45
-        g[3] = hxp ? ldb(gi, kb + 3 * Pb + E) : c.cold - ldb(gi, kb + Pb);
+        // one read per link, the address selected, so no read sits in a
+        // branch; Eq. 45 is applied to the value afterwards.  Every launch
+        // shape has rows of a multiple of 64 threads, so y is uniform per
+        // wavefront and the wall temperature is one scalar read.
+        const real g1 = ldb(gi, hxm ? kb + Pb - E : kb + 3 * Pb);
+        const real g3 = ldb(gi, hxp ? kb + 3 * Pb + E : kb + Pb);
+        const real tw = thw_row<real>(thw, __builtin_amdgcn_readfirstlane(y));
+        g[1] = hxm ? g1 : fmr(c.cabb, tw, -g1);                      // Eq. 45
+        g[3] = hxp ? g3 : c.cold - g3;
         return;
     }
     constexpr bool PX = (BC == BC_PERIODIC || BC == BC_CHANNEL_X);
@@ -298,16 +315,6 @@ __device__ __forceinline__ void gather(const real* __restrict__ fi, const real* 
         g[1] = hxm ? gi[1 * P + k + dxm] : gi[3 * P + k];
         g[3] = hxp ? gi[3 * P + k + dxp] : gi[1 * P + k];
     }
-}
-
-// Wall temperature of row y, uniform per wave: a scalar load through the
-// constant address space, which does not wait for vector memory operations
-// in flight.
-template <typename real>
-__device__ __forceinline__ real thw_row(const real* thw, int y)
-{
-    typedef const __attribute__((address_space(4))) real creal;
-    return ((creal*)thw)[y];
 }
 
 // The cavity gather split in two for prefetching: the loads alone, with
