@@ -35,6 +35,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD published)
 # (614.4 G wave instructions/s; 78.6 TFLOP/s if every one were an FMA).
 VALU_PEAK_GINSTR = 256 * 4 * 2.4 / 4
 WORDS_PER_NODE = 28            # 14 populations read + 14 written per node and launch
+# Algorithmic arithmetic of a node update: the 112 floating-point
+# instructions of the collision (moments, equilibria, force image,
+# relaxation and back-transform; streaming is data movement), i.e. 112 wave
+# instructions per 64 node updates.
+ALG_VALU_PER_NODE = 112
 # committed counter summaries, by (kernel, cavity side)
 TRAFFIC_FILES = {
     ("step_kernel<float, 0>", 1024): "step_kernel_cavity_1024_fp32_traffic.json",
@@ -93,11 +98,14 @@ def roofline(kernel, esz, n, spl, us_launch, counters):
 
     HBM: a launch must read and write every population of every node once,
     whatever spl (the intermediate states of a K-step launch stay on chip):
-    28 words x n^2 algorithmic bytes per launch.  ALU: the wave64 vector
-    instructions a launch issues (SQ_INSTS_VALU of the committed counter
-    summary, which holds while the kernel source is unchanged) against the
-    issue peak.  `bound` is the one of the two closer to its peak; the other
-    is reported beside it.  effective_GBs is 28 words per node update (K n^2
+    28 words x n^2 algorithmic bytes per launch.  ALU: the algorithmic
+    instructions of the spl n^2 node updates (ALG_VALU_PER_NODE per node
+    update, 64 node updates per wave instruction) against the issue peak,
+    with the instructions the launch actually issues (SQ_INSTS_VALU of the
+    committed counter summary, which holds while the kernel source is
+    unchanged) beside them.  `bound` is instruction issue when the issued
+    rate is closer to its peak than the HBM rate is to its own, else HBM;
+    the other is reported beside it.  effective_GBs is 28 words per node update (K n^2
     node updates per launch) over the launch time: above the HBM peak for
     K >= 2 because K - 1 of the K steps never leave the chip."""
     t = us_launch * 1e-6
@@ -111,11 +119,18 @@ def roofline(kernel, esz, n, spl, us_launch, counters):
         traffic = counters.get("bytes_per_launch")
         vi = counters.get("valu_instructions_per_launch")
         if vi:
-            alu = {"achieved": round(vi / t / 1e9, 1), "peak": VALU_PEAK_GINSTR, "unit": "Ginstr/s",
-                   "frac": round(vi / t / 1e9 / VALU_PEAK_GINSTR, 4),
+            alg = spl * n * n * ALG_VALU_PER_NODE / 64
+            alu = {"achieved": round(alg / t / 1e9, 1), "peak": VALU_PEAK_GINSTR, "unit": "Ginstr/s",
+                   "frac": round(alg / t / 1e9 / VALU_PEAK_GINSTR, 4),
+                   "algorithmic_instructions_per_launch": round(alg),
+                   "issued_Ginstr_s": round(vi / t / 1e9, 1),
+                   "issued_frac": round(vi / t / 1e9 / VALU_PEAK_GINSTR, 4),
                    "valu_instructions_per_launch": vi,
                    "valu_busy_frac_counters": counters.get("valu_busy_frac")}
-    main, other, bound = (alu, hbm, "alu") if alu and alu["frac"] > hbm["frac"] else (hbm, alu, "hbm")
+    # the binding resource by the counters: instruction issue when the
+    # issued VALU rate is closer to its peak than the HBM rate is to its own
+    issue_binds = alu is not None and alu["issued_frac"] > hbm["frac"]
+    main, other, bound = (alu, hbm, "alu") if issue_binds else (hbm, alu, "hbm")
     out = {"bound": bound, "achieved": main["achieved"], "peak": main["peak"], "unit": main["unit"],
            "frac": main["frac"], "traffic": traffic, "kernel": kernel,
            "launch_us": round(us_launch, 3), "steps_per_launch": spl,
@@ -125,8 +140,9 @@ def roofline(kernel, esz, n, spl, us_launch, counters):
     if bound == "hbm":
         out["algorithmic_bytes_per_launch"] = hbm_bytes
     else:
-        out["valu_instructions_per_launch"] = alu["valu_instructions_per_launch"]
-        out["valu_busy_frac_counters"] = alu["valu_busy_frac_counters"]
+        for key in ("algorithmic_instructions_per_launch", "issued_Ginstr_s", "issued_frac",
+                    "valu_instructions_per_launch", "valu_busy_frac_counters"):
+            out[key] = alu[key]
     if traffic:
         out["traffic_over_algorithmic"] = round(traffic / hbm_bytes, 4)
     return out
