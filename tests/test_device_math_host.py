@@ -32,6 +32,10 @@ def host_lib():
     for name in ("dmrt_host_collide", "dmrt_host_collide_vjp"):
         getattr(lib, name).argtypes = [ctypes.c_void_p, ctypes.c_void_p, dp, dp, dp, dp]
         getattr(lib, name).restype = ctypes.c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    for name, ptr in (("dmrt_host_vjp_paths_f64", dp), ("dmrt_host_vjp_paths_f32", fp)):
+        getattr(lib, name).argtypes = [ctypes.c_void_p, ctypes.c_void_p, ptr, ptr, ptr, ptr, ptr]
+        getattr(lib, name).restype = ctypes.c_int
     return lib
 
 
@@ -154,3 +158,35 @@ def test_collision_vjp_dot_product_identity(host_lib):
         rhs = a @ vf[:, 0, k] + b @ vg[:, 0, k]
         scale = np.abs(wf[:, 0, k]).sum() + np.abs(wg[:, 0, k]).sum()
         assert abs(lhs[k] - rhs) <= 1e-13 * scale, (k, lhs[k], rhs)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_vjp_at_forward_point_is_bitwise_the_state_vjp(host_lib, dtype):
+    """The backward stores only the u, v, theta that the forward collision
+    returns and forms the transposed Jacobian from them: that must be
+    bitwise the transposed Jacobian formed from the whole pre-collision
+    state (the Jacobian depends on the state only through u, v, theta), in
+    both storage precisions, for states across the moment ranges of the
+    cavity runs (including walls' extreme temperatures)."""
+    p, d = _params(Ra=1e4, Pr=0.01, n=256)
+    rng = np.random.default_rng(4633)
+    name = "dmrt_host_vjp_paths_f64" if dtype == np.float64 else "dmrt_host_vjp_paths_f32"
+    ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+    fn = getattr(host_lib, name)
+
+    def ptr(a):
+        return a.ctypes.data_as(ctypes.POINTER(ct))
+
+    count = 0
+    for scale_f, scale_g in ((1e-6, 1e-4), (0.05, 0.3), (0.2, 0.6)):
+        for f, g in _states(rng, 200, scale_f, scale_g):
+            f = f.astype(dtype)
+            g = g.astype(dtype)
+            lam = rng.normal(size=14).astype(dtype)
+            a = np.zeros(14, dtype)
+            b = np.zeros(14, dtype)
+            fn(ctypes.byref(p), ctypes.byref(d), ptr(f), ptr(g), ptr(lam), ptr(a), ptr(b))
+            assert np.isfinite(a).all()
+            assert a.tobytes() == b.tobytes(), (f, g, lam, a, b)
+            count += 1
+    assert count == 600
