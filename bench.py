@@ -286,12 +286,17 @@ def batch_roofline(mlups, cfg):
     """The batched launches move every population of every member once per
     launch: 28 words x 4 B per node per launch, i.e. 112 / K B per node
     update with K steps per launch."""
-    K = int(cfg["temporal"][0]) if cfg else 1
+    t = tuple(cfg["temporal"]) if cfg else (1, 10)
+    if t[0] == "march":
+        K = int(t[1])
+        kernel = f"batch_stepm_kernel<float, {K}, {int(t[2])}>"
+    else:
+        K = int(t[0])
+        kernel = f"batch_stepk_kernel<float, {t[1]}, {K}>" if K >= 2 else "batch_step_kernel<float>"
     gbs = mlups * 1e6 * WORDS_PER_NODE * 4 / K / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"batch_stepk_kernel<float, {cfg['temporal'][1]}, {K}>" if K >= 2
-            else "batch_step_kernel<float>",
+            "kernel": kernel,
             "bytes_per_node_update": WORDS_PER_NODE * 4 / K, "steps_per_launch": K,
             "effective_GBs": round(mlups * 1e6 * WORDS_PER_NODE * 4 / 1e9, 1)}
 

@@ -403,6 +403,19 @@ int dmrt_batch_set_schedule(dmrt_batch *b, int block_x, int block_y, int order, 
  * Results do not depend on it. */
 int dmrt_batch_set_temporal(dmrt_batch *b, int steps_per_launch, int tile_rows);
 
+/* K = steps_per_launch steps per launch with the row-marching sweep of
+ * dmrt_set_temporal_march (same Eqs. 25-45, same (K, group_rows) pairs and
+ * LDS rings): every workgroup takes one member's column band and chunk of
+ * rows, so each member evolves bitwise as it would alone.  chunk_rows >= 1
+ * rows per workgroup for every member of a group, or 0 for, per group, the
+ * shortest chunk that leaves all of the group's workgroups resident on the
+ * device at once.  The table deals each die a contiguous range of
+ * workgroups.  Remainders of a group's steps go one per launch.
+ * dmrt_batch_set_temporal switches the marching off.  EINVAL for a pair
+ * not built or whose rings exceed 160 KB in the batch's precision; EHIP if
+ * the device query for chunk_rows = 0 fails. */
+int dmrt_batch_set_temporal_march(dmrt_batch *b, int steps_per_launch, int group_rows, int chunk_rows);
+
 /* Advance every live member nsteps >= 0 steps.  Enqueued only. */
 int dmrt_batch_step(dmrt_batch *b, long nsteps);
 int dmrt_batch_sync(dmrt_batch *b);

@@ -8,7 +8,9 @@ in a JSON file keyed by (device architecture, precision, member sizes).
 
 Batch schedule dimensions (dmrt_batch_set_schedule): tile shape, tile
 order, workgroups per launch, and cavity groups sized for the 256 MB
-last-level cache that run several steps before the next group.
+last-level cache that run several steps before the next group; steps per
+launch with the tile form (dmrt_batch_set_temporal) or the row-marching
+form (dmrt_batch_set_temporal_march, entries ("march", K, B)).
 Single-cavity dimensions: steps per launch with the tile kernel and its
 rows (dmrt_set_temporal) or with the row-marching kernel and its wave rows
 per step group (dmrt_set_temporal_march, entries ("march", K, B)), tile
@@ -28,15 +30,18 @@ CACHE_PATH = os.environ.get("DMRT_AUTOTUNE_CACHE",
 MB = 1 << 20
 
 BATCH_SPACE = {
-    "temporal": [(4, 16), (4, 12), (3, 16), (3, 12), (2, 6), (2, 10), (3, 10), (4, 10), (1, 10)],
+    "temporal": [(4, 16), ("march", 4, 3), ("march", 6, 2), ("march", 4, 4), ("march", 4, 2), (4, 12),
+                 (3, 16), (3, 12), (2, 6), (2, 10), (3, 10), (4, 10), (1, 10)],
     "block": [(64, 4), (64, 2), (64, 8), (128, 2), (128, 4), (256, 1), (64, 1)],
     "order": [1, 0, 2],
     "grid_blocks": [0, 4096, 16384],
-    "group": [(0, 64), (96 * MB, 8), (96 * MB, 32), (160 * MB, 16), (160 * MB, 64),
-              (224 * MB, 32)],
+    # steps per group round: multiples of 12, so that every steps-per-launch
+    # choice (1, 2, 3, 4, 6) divides them and no round ends in single steps
+    "group": [(0, 60), (96 * MB, 12), (96 * MB, 36), (160 * MB, 24), (160 * MB, 60),
+              (224 * MB, 36)],
 }
 BATCH_DEFAULT = {"temporal": (4, 16), "block": (64, 4), "order": 1, "grid_blocks": 0,
-                 "group": (0, 64)}
+                 "group": (0, 60)}
 
 CAVITY_SPACE = {
     "temporal": [(4, 16), ("march", 4, 3), ("march", 4, 2), ("march", 4, 4), ("march", 6, 2), ("march", 4, 1), (4, 12),
@@ -140,7 +145,11 @@ def apply_batch(batch, cfg):
     gb, gs = cfg["group"]
     batch.set_schedule(block_x=bx, block_y=by, order=cfg["order"],
                        grid_blocks=cfg["grid_blocks"], group_bytes=gb, group_steps=gs)
-    batch.set_temporal(*cfg.get("temporal", (1, 10)))
+    t = tuple(cfg.get("temporal", (1, 10)))
+    if t[0] == "march":
+        batch.set_temporal_march(t[1], t[2], t[3] if len(t) > 3 else 0)
+    else:
+        batch.set_temporal(*t)
 
 
 def tune_batch(batch, stream_ptr=None, min_steps=128, use_cache=True, verbose=False):

@@ -13,6 +13,9 @@
 // groups: members are packed in order into groups of at most `group_bytes`
 // of state, and each group runs `group_steps` steps before the next group
 // starts, so a group small enough for the last-level cache stays there.
+// Steps per launch: one, K through LDS on overlapping footprints (the tile
+// form), or K with the row-marching sweep, each workgroup taking one
+// (member, column band, chunk of rows) of its group.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,6 +56,11 @@ struct dmrt_batch {
     TileRef* foot_tiles = nullptr;           // footprints of the K-step kernel
     std::vector<int> group_foot_begin;
     int temporal = 1, t_rows = 10;       // steps per launch and footprint rows
+    // row-marching form (march_B > 0: wave rows per step group; chunk rows,
+    // 0 = chosen per group so that its workgroups are resident at once)
+    int march_B = 0, march_chunk = 0;
+    MarchRef* march_tiles = nullptr;
+    std::vector<int> group_march_begin;
     int graph_flips[2] = {0, 0};
     double* nu = nullptr;
     int* flags = nullptr;
@@ -153,6 +161,86 @@ int upload_hot_walls(dmrt_batch* b)
     return DMRT_OK;
 }
 
+// Resident workgroups per CU of the batched marching kernel (K, B) in the
+// batch's precision, or -1.
+template <typename real>
+int march_per_cu(int K, int B)
+{
+    int per_cu = 0;
+#define DMRT_KB_OCC(KK, BB)                                                                           \
+    if constexpr (march_lds_bytes(KK, BB, sizeof(real)) <= kLdsBytes)                                  \
+        if (K == KK && B == BB &&                                                                     \
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_stepm_kernel<real, KK, BB>,    \
+                                                         kFootW * KK * BB, 0) != hipSuccess)           \
+            return -1;
+    DMRT_FOR_EACH_KB(DMRT_KB_OCC)
+#undef DMRT_KB_OCC
+    return per_cu > 0 ? per_cu : -1;
+}
+
+// The row-marching table: for every group, its members' (column band,
+// chunk) pairs, member by member, chunk rows row-major, odd chunks marching
+// down; then dealt so that each of the 8 dies gets a contiguous range (the
+// dispatcher deals workgroups round-robin over the dies; unused slots have
+// cav = -1).  The chunk length of a group is march_chunk, or else the
+// shortest that leaves all of the group's workgroups resident at once.
+int build_march_tiles(dmrt_batch* b, const std::vector<std::vector<int>>& groups)
+{
+    b->group_march_begin.clear();
+    if (b->march_tiles) { (void)hipFree(b->march_tiles); b->march_tiles = nullptr; }
+    if (b->march_B <= 0) return DMRT_OK;
+    const int K = b->temporal, B = b->march_B;
+    const int W = kFootW - 2 * (K - 1);
+    int slots = 0;
+    if (b->march_chunk <= 0) {
+        int cus = 0;
+        HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->dev));
+        const int per_cu = b->esz == 8 ? march_per_cu<double>(K, B) : march_per_cu<float>(K, B);
+        if (per_cu <= 0 || cus <= 0) {
+            set_last_error("batch marching schedule: occupancy query failed");
+            return DMRT_EHIP;
+        }
+        slots = per_cu * cus;
+    }
+    std::vector<MarchRef> all;
+    for (const auto& g : groups) {
+        b->group_march_begin.push_back((int)all.size());
+        int chunk = b->march_chunk;
+        if (chunk <= 0) {
+            int nmax = 1;
+            for (int i : g) nmax = std::max(nmax, b->p[i].n);
+            chunk = nmax;
+            for (int c = 1; c <= nmax; ++c) {
+                long wgs = 0;
+                for (int i : g) {
+                    const int n = b->p[i].n;
+                    wgs += (long)((n + W - 1) / W) * ((n + c - 1) / c);
+                }
+                if (wgs <= slots) { chunk = c; break; }
+            }
+        }
+        std::vector<MarchRef> list;
+        for (int i : g) {
+            const int n = b->p[i].n, tiles_x = (n + W - 1) / W;
+            for (int ty = 0, y0 = 0; y0 < n; ++ty, y0 += chunk)
+                for (int tx = 0; tx < tiles_x; ++tx)
+                    list.push_back({i, tx * W - (K - 1), y0, std::min(y0 + chunk, n) | ((ty & 1) << 30)});
+        }
+        const int per = ((int)list.size() + 7) / 8;
+        std::vector<MarchRef> dealt((size_t)per * 8, MarchRef{-1, 0, 0, 0});
+        for (int blk = 0; blk < per * 8; ++blk) {
+            const int t = (blk & 7) * per + (blk >> 3);
+            if (t < (int)list.size()) dealt[blk] = list[t];
+        }
+        all.insert(all.end(), dealt.begin(), dealt.end());
+    }
+    b->group_march_begin.push_back((int)all.size());
+    HIPCHK(hipMalloc(&b->march_tiles, all.size() * sizeof(MarchRef)));
+    HIPCHK(hipMemcpyAsync(b->march_tiles, all.data(), all.size() * sizeof(MarchRef), hipMemcpyHostToDevice,
+                          b->stream));
+    return DMRT_OK;
+}
+
 // Builds the tile table and the group ranges for the current schedule.
 int build_tiles(dmrt_batch* b)
 {
@@ -203,13 +291,16 @@ int build_tiles(dmrt_batch* b)
     HIPCHK(hipMalloc(&b->tiles, tiles.size() * sizeof(TileRef)));
     HIPCHK(hipMemcpyAsync(b->tiles, tiles.data(), tiles.size() * sizeof(TileRef),
                           hipMemcpyHostToDevice, b->stream));
-    // footprints of the K-step kernel, same groups and member order
+    // footprints of the K-step tile kernel, same groups and member order
+    // (none in the row-marching form)
     std::vector<TileRef> fp;
     b->group_foot_begin.clear();
+    const bool tile_form = b->march_B <= 0 && b->temporal <= 4;
     const int K = std::max(2, b->temporal), R = b->t_rows;
     const int W = kFootW - 2 * (K - 1), HO = R - 2 * (K - 1);
     for (const auto& g : groups) {
         b->group_foot_begin.push_back((int)fp.size());
+        if (!tile_form || HO <= 0) continue;
         for (int i : g) {
             const int n = b->p[i].n;
             for (int y0 = 0; y0 < n; y0 += HO)
@@ -218,9 +309,11 @@ int build_tiles(dmrt_batch* b)
     }
     b->group_foot_begin.push_back((int)fp.size());
     if (b->foot_tiles) { (void)hipFree(b->foot_tiles); b->foot_tiles = nullptr; }
-    HIPCHK(hipMalloc(&b->foot_tiles, fp.size() * sizeof(TileRef)));
+    HIPCHK(hipMalloc(&b->foot_tiles, std::max<size_t>(1, fp.size()) * sizeof(TileRef)));
     HIPCHK(hipMemcpyAsync(b->foot_tiles, fp.data(), fp.size() * sizeof(TileRef), hipMemcpyHostToDevice,
                           b->stream));
+    int rc = build_march_tiles(b, groups);
+    if (rc) return rc;
     HIPCHK(hipStreamSynchronize(b->stream));
     return DMRT_OK;
 }
@@ -264,6 +357,26 @@ int launch_rangek_t(dmrt_batch* b, hipStream_t s, int t0, int t1, int from)
     return DMRT_EINVAL;
 }
 
+template <typename real>
+int launch_rangem_t(dmrt_batch* b, hipStream_t s, int t0, int t1, int from)
+{
+    const int span = t1 - t0;
+    if (span <= 0) return DMRT_OK;
+    const CavityDev<real>* cv = static_cast<const CavityDev<real>*>(b->cavs);
+    const int K = b->temporal, B = b->march_B;
+#define DMRT_BKB(KK, BB)                                                                               \
+    if constexpr (march_lds_bytes(KK, BB, sizeof(real)) <= kLdsBytes)                                    \
+        if (K == KK && B == BB) {                                                                       \
+            hipLaunchKernelGGL((batch_stepm_kernel<real, KK, BB>), dim3(span), dim3(kFootW, KK * BB), 0, s, \
+                               cv, b->march_tiles, t0, t1, from);                                       \
+            HIPCHK(hipGetLastError());                                                                  \
+            return DMRT_OK;                                                                             \
+        }
+    DMRT_FOR_EACH_KB(DMRT_BKB)
+#undef DMRT_BKB
+    return DMRT_EINVAL;
+}
+
 // One round: each group in turn advances `steps` steps (K steps per launch
 // when the K-step kernel is selected).  *flips receives the
 // number of launches per group (each moves the state to the other copy).
@@ -276,7 +389,11 @@ int enqueue_round(dmrt_batch* b, hipStream_t s, int from, int steps, int* flips)
         nf = 0;
         while (k > 0) {
             int rc;
-            if (b->temporal >= 2 && k >= b->temporal) {
+            if (b->temporal >= 2 && k >= b->temporal && b->march_B > 0) {
+                const int m0 = b->group_march_begin[g], m1 = b->group_march_begin[g + 1];
+                rc = b->esz == 8 ? launch_rangem_t<double>(b, s, m0, m1, c) : launch_rangem_t<float>(b, s, m0, m1, c);
+                k -= b->temporal;
+            } else if (b->temporal >= 2 && k >= b->temporal) {
                 rc = b->esz == 8 ? launch_rangek_t<double>(b, s, b->group_foot_begin[g], b->group_foot_begin[g + 1], c)
                                  : launch_rangek_t<float>(b, s, b->group_foot_begin[g], b->group_foot_begin[g + 1], c);
                 k -= b->temporal;
@@ -459,6 +576,19 @@ int dmrt_batch_set_temporal(dmrt_batch* b, int steps_per_launch, int tile_rows)
     drop_graphs(b);
     b->temporal = steps_per_launch;
     b->t_rows = tile_rows;
+    b->march_B = 0;
+    return build_tiles(b);
+}
+
+int dmrt_batch_set_temporal_march(dmrt_batch* b, int steps_per_launch, int group_rows, int chunk_rows)
+{
+    if (!b || chunk_rows < 0) return DMRT_EINVAL;
+    if (!valid_march(steps_per_launch, group_rows, (int)b->esz)) return DMRT_EINVAL;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    b->temporal = steps_per_launch;
+    b->march_B = group_rows;
+    b->march_chunk = chunk_rows;
     return build_tiles(b);
 }
 
@@ -617,8 +747,8 @@ int dmrt_batch_destroy(dmrt_batch* b)
     if (!b) return DMRT_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graphs(b);
-    void* ptrs[] = {b->arena, b->thw_real, b->thw_d, b->cavs, b->tiles, b->foot_tiles, b->nu, b->flags,
-                    b->scratch};
+    void* ptrs[] = {b->arena, b->thw_real, b->thw_d, b->cavs, b->tiles, b->foot_tiles, b->march_tiles,
+                    b->nu, b->flags, b->scratch};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);

@@ -1104,34 +1104,29 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
     __syncthreads();
 }
 
+// One workgroup's sweep: the column band whose footprint starts at column
+// x_band (64 lanes, output columns x_band + K - 1 ... x_band + 64 - K) over
+// the chunk of rows [y0, y1), marching down the rows when `down`; lds holds
+// the K - 1 rings of 14 planes x (B + 2) rows x 64.
 template <typename real, int K, int B>
-__global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A, int chunk)
+__device__ __forceinline__ void stepm_sweep(const StepArgs<real>& A, real* lds, int x_band, int y0, int y1,
+                                            bool down)
 {
-    constexpr int RS = B + 2, W = kFootW - 2 * (K - 1), RING = 14 * RS * kFootW;
-    static_assert(K >= 2 && W > 0, "K out of range");
-    __shared__ real lds[(K - 1) * RING];
-    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
-    if (tile >= A.tiles) return;                      // uniform per workgroup
-    const int tyt = tile / A.tiles_x;
-    const int txt = tile - tyt * A.tiles_x;
+    constexpr int RS = B + 2, RING = 14 * RS * kFootW;
     MarchWave<real> w;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);   // blockDim.x = 64: one wave per y index
     w.j = wv / B + 1;
     w.r = wv - (w.j - 1) * B;
     w.lx = threadIdx.x;
-    w.x = txt * W - (K - 1) + w.lx;
+    w.x = x_band + w.lx;
     const int n = A.n;
-    const int y0 = tyt * chunk, y1 = min(y0 + chunk, n);
     const int a1 = y0 - (K - 1);
     w.aj = a1 - (w.j - 1) * (B + 1);
     w.aK = a1 - (K - 1) * (B + 1);
     const int T = (y1 - 1 - w.aK) / B + 1;            // iterations until group K has passed y1 - 1
     w.lo = y0 - (K - w.j);
     w.hi = y1 + (K - w.j);
-    // odd chunks march down (row y0 + y1 - 1 - v for marching row v), so
-    // that two neighbouring chunks read the rows they share at the same
-    // time, at the end of both sweeps or at the start of both
-    w.down = (tyt & 1) != 0;
+    w.down = down;
     w.ymir = y0 + y1 - 1;
     w.y0 = y0;
     w.y1 = y1;
@@ -1153,6 +1148,23 @@ __global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A,
     } else {
         for (int i = 0; i < T; ++i) march_iter<real, K, B, false>(A, w, i, af, ag, bf, bg);
     }
+}
+
+template <typename real, int K, int B>
+__global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A, int chunk)
+{
+    constexpr int RS = B + 2, W = kFootW - 2 * (K - 1), RING = 14 * RS * kFootW;
+    static_assert(K >= 2 && W > 0, "K out of range");
+    __shared__ real lds[(K - 1) * RING];
+    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (tile >= A.tiles) return;                      // uniform per workgroup
+    const int tyt = tile / A.tiles_x;
+    const int txt = tile - tyt * A.tiles_x;
+    const int y0 = tyt * chunk;
+    // odd chunks march down (row y0 + y1 - 1 - v for marching row v), so
+    // that two neighbouring chunks read the rows they share at the same
+    // time, at the end of both sweeps or at the start of both
+    stepm_sweep<real, K, B>(A, lds, txt * W - (K - 1), y0, min(y0 + chunk, A.n), (tyt & 1) != 0);
 }
 
 // lambda at footprint node (lx, ly) from mu of the previous phase in LDS:
@@ -1553,6 +1565,45 @@ __global__ void __launch_bounds__(kFootW * R) batch_stepk_kernel(
                                lx, ly, cv.c);
         __syncthreads();                              // the next tile reuses the LDS
     }
+}
+
+// One entry per workgroup of the batched row-marching kernel: cavity, first
+// footprint column of the band, and the chunk's rows [y0, y1) with the
+// marching direction in bit 30 of y1d (cav < 0: an unused slot of the
+// die-aware table).
+struct MarchRef {
+    int cav, x0, y0, y1d;
+};
+
+// K steps of many cavities in one launch with the row-marching sweep: each
+// workgroup takes one (cavity, band, chunk) entry and runs the same sweep
+// as stepm_kernel on that cavity, so every member evolves bitwise as it
+// would alone.  All cavities step from copy `cur` to `cur ^ 1`.
+template <typename real, int K, int B>
+__global__ void __launch_bounds__(kFootW * K * B) batch_stepm_kernel(const CavityDev<real>* __restrict__ cavs,
+                                                                     const MarchRef* __restrict__ tiles,
+                                                                     int t_begin, int t_end, int cur)
+{
+    constexpr int RS = B + 2, W = kFootW - 2 * (K - 1), RING = 14 * RS * kFootW;
+    static_assert(K >= 2 && W > 0, "K out of range");
+    __shared__ real lds[(K - 1) * RING];
+    const int t = t_begin + (int)blockIdx.x;
+    if (t >= t_end) return;
+    const MarchRef tr = tiles[t];
+    if (tr.cav < 0) return;                           // uniform per workgroup
+    const CavityDev<real>& cv = cavs[tr.cav];
+    if (cv.dead) return;
+    StepArgs<real> A;
+    A.fin = cv.f[cur];
+    A.gin = cv.g[cur];
+    A.fout = cv.f[cur ^ 1];
+    A.gout = cv.g[cur ^ 1];
+    A.thw = cv.thw;
+    A.n = cv.n;
+    A.pitch = cv.pitch;
+    A.plane = cv.plane;
+    A.c = cv.c;
+    stepm_sweep<real, K, B>(A, lds, tr.x0, tr.y0, tr.y1d & 0x3fffffff, ((tr.y1d >> 30) & 1) != 0);
 }
 
 // Hot-wall Nusselt number of every cavity of a batch: one workgroup each.

@@ -112,6 +112,7 @@ _SIGS = {
     "dmrt_batch_set_hot_wall": [_vp, _c_int, _dp],
     "dmrt_batch_set_schedule": [_vp, _c_int, _c_int, _c_int, _c_int, _c_size, _c_int],
     "dmrt_batch_set_temporal": [_vp, _c_int, _c_int],
+    "dmrt_batch_set_temporal_march": [_vp, _c_int, _c_int, _c_int],
     "dmrt_batch_step": [_vp, _c_long],
     "dmrt_batch_sync": [_vp],
     "dmrt_batch_get_step": [_vp, ctypes.POINTER(_c_long)],
@@ -445,6 +446,12 @@ class Batch:
 
     def set_temporal(self, steps_per_launch=4, tile_rows=16):
         check(dmrt_batch_set_temporal(self._h, steps_per_launch, tile_rows), "dmrt_batch_set_temporal")
+
+    def set_temporal_march(self, steps_per_launch=4, group_rows=3, chunk_rows=0):
+        """K steps per launch with the row-marching sweep (one member's
+        column band and chunk of rows per workgroup)."""
+        check(dmrt_batch_set_temporal_march(self._h, steps_per_launch, group_rows, chunk_rows),
+              "dmrt_batch_set_temporal_march")
 
     def step(self, nsteps=1):
         check(dmrt_batch_step(self._h, int(nsteps)), "dmrt_batch_step")

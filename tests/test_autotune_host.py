@@ -72,6 +72,9 @@ class _FakeBatch:
     def set_temporal(self, *a):
         self.calls.append(("temporal", a))
 
+    def set_temporal_march(self, *a):
+        self.calls.append(("march", a))
+
 
 def test_apply_functions_call_the_setters():
     c = _FakeCavity()
@@ -90,6 +93,10 @@ def test_apply_functions_call_the_setters():
     assert b.calls[0] == ("schedule", dict(block_x=64, block_y=4, order=2, grid_blocks=4096,
                                            group_bytes=96 << 20, group_steps=8))
     assert b.calls[1] == ("temporal", (3, 16))
+    bm = _FakeBatch()                 # the marching form, as read back from the JSON cache
+    autotune.apply_batch(bm, {"temporal": ["march", 6, 2], "block": [64, 4], "order": 1, "grid_blocks": 0,
+                              "group": [0, 64]})
+    assert bm.calls[1] == ("march", (6, 2, 0)) and not any(k == "temporal" for k, _ in bm.calls)
 
 
 def test_search_spaces_only_hold_supported_pairs():
@@ -98,9 +105,9 @@ def test_search_spaces_only_hold_supported_pairs():
     ok = {(1, 4), (1, 6), (1, 10), (1, 16), (2, 4), (2, 6), (2, 10), (2, 16), (3, 6), (3, 10), (3, 12),
           (3, 14), (3, 16), (4, 10), (4, 12), (4, 14), (4, 16)}
     march_ok = {(2, 8), (3, 2), (3, 4), (4, 1), (4, 2), (4, 3), (4, 4), (6, 2)}   # dmrt_set_temporal_march
-    for kr in autotune.BATCH_SPACE["temporal"] + autotune.ADJOINT_SPACE:
+    for kr in autotune.ADJOINT_SPACE:
         assert tuple(kr) in ok, kr
-    for kr in autotune.CAVITY_SPACE["temporal"]:
+    for kr in autotune.CAVITY_SPACE["temporal"] + autotune.BATCH_SPACE["temporal"]:
         if kr[0] == "march":
             assert tuple(kr[1:3]) in march_ok, kr
         else:

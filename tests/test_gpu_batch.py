@@ -27,7 +27,24 @@ SCHEDULES = [
     dict(block_x=64, block_y=4, order=2, grid_blocks=500, group_bytes=3 << 20, group_steps=10,
          temporal=(3, 10)),
     dict(block_x=256, block_y=1, order=0, grid_blocks=0, group_bytes=0, group_steps=11, temporal=(4, 16)),
+    # row-marching form: automatic chunks (one resident round), fixed short
+    # chunks, cavity groups, six steps per launch, the two-step form
+    dict(block_x=64, block_y=4, order=1, grid_blocks=0, group_bytes=0, group_steps=64,
+         temporal=("march", 4, 3, 0)),
+    dict(block_x=128, block_y=2, order=2, grid_blocks=0, group_bytes=3 << 20, group_steps=12,
+         temporal=("march", 4, 2, 9)),
+    dict(block_x=256, block_y=1, order=0, grid_blocks=0, group_bytes=0, group_steps=30,
+         temporal=("march", 6, 2, 0)),
+    dict(block_x=64, block_y=4, order=1, grid_blocks=0, group_bytes=0, group_steps=16,
+         temporal=("march", 2, 8, 5)),
 ]
+
+
+def _apply_temporal(b, temporal):
+    if temporal[0] == "march":
+        b.set_temporal_march(*temporal[1:])
+    else:
+        b.set_temporal(*temporal)
 
 
 def _single(member, precision, th0, steps):
@@ -47,7 +64,7 @@ def test_batch_members_bitwise_equal_single(precision, sched):
     sc = dict(SCHEDULES[sched])
     temporal = sc.pop("temporal", (1, 10))
     b.set_schedule(**sc)
-    b.set_temporal(*temporal)
+    _apply_temporal(b, temporal)
     th = [inputs.theta_noise(m["n"], 100 + i, amp=1e-3) for i, m in enumerate(MEMBERS)]
     for i, t in enumerate(th):
         b.set_theta(i, t)
@@ -144,7 +161,7 @@ def test_sweep_shaped_batch_sampled_members():
         assert nu[i] == c.nusselt(0)[0]
 
 
-@pytest.mark.parametrize("temporal", [(1, 10), (2, 6), (4, 16)])
+@pytest.mark.parametrize("temporal", [(1, 10), (2, 6), (4, 16), ("march", 4, 3, 0), ("march", 6, 2, 3)])
 def test_tiny_and_ragged_members_bitwise_equal_single(temporal):
     """Members smaller than one footprint (4^2, 5^2) and ragged sizes beside
     a larger one, K steps per launch: every member equals its single run."""
@@ -152,7 +169,7 @@ def test_tiny_and_ragged_members_bitwise_equal_single(temporal):
     members = [dict(n=4, Ra=1e4, Pr=0.01), dict(n=5, Ra=3e3, Pr=0.005), dict(n=59, Ra=1e4, Pr=0.01),
                dict(n=131, Ra=5e4, Pr=0.005)]
     b = Batch(members, precision="fp32")
-    b.set_temporal(*temporal)
+    _apply_temporal(b, temporal)
     th = [inputs.theta_noise(m["n"], 70 + i, amp=1e-2) for i, m in enumerate(members)]
     for i, t in enumerate(th):
         b.set_theta(i, t)
@@ -189,4 +206,31 @@ def test_sweep_in_benchmark_schedule_sampled_members():
     for i in sorted(picks):
         c = _single(members[i], "fp32", th[i], 224)
         assert np.array_equal(b.raw_state(i)[0], c.raw_state()[0]), i
+        assert nu[i] == c.nusselt(0)[0]
+
+
+@pytest.mark.parametrize("temporal", [("march", 4, 3, 0), ("march", 6, 2, 0)])
+def test_sweep_in_marching_schedule_sampled_members(temporal):
+    """The 64-cavity sweep with the row-marching form (every member's bands
+    and chunks in one launch per group, 224 MB groups of 32 steps): sampled
+    members of every side equal their single runs bitwise."""
+    from paper_1601_04633_amd.dmrt import Batch
+    specs = inputs.batch_cavities(64, 4633)
+    members = [dict(n=s, Ra=ra, Pr=pr) for s, ra, pr in specs]
+    b = Batch(members, precision="fp32")
+    b.set_schedule(block_x=256, block_y=1, order=1, grid_blocks=0, group_bytes=224 << 20, group_steps=32)
+    _apply_temporal(b, temporal)
+    th = {}
+    for i, m in enumerate(members):
+        th[i] = inputs.theta_noise(m["n"], 4633 + i)
+        b.set_theta(i, th[i])
+    b.step(96)
+    nu = b.nusselt()
+    assert np.all(np.isfinite(nu))
+    sides = [m["n"] for m in members]
+    picks = {sides.index(s) for s in set(sides)} | {len(members) - 1}
+    for i in sorted(picks):
+        c = _single(members[i], "fp32", th[i], 96)
+        assert np.array_equal(b.raw_state(i)[0], c.raw_state()[0]), (i, temporal)
+        assert np.array_equal(b.raw_state(i)[1], c.raw_state()[1]), (i, temporal)
         assert nu[i] == c.nusselt(0)[0]
