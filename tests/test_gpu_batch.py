@@ -139,6 +139,35 @@ def test_dead_member_is_flagged_and_skipped():
     assert b.status()[2] == 0
 
 
+def test_dead_member_skipped_by_the_marching_form():
+    """A member planted with NaN is flagged and skipped by the batched
+    marching launches (six steps each) while the others keep matching
+    their single runs bitwise."""
+    from paper_1601_04633_amd.dmrt import Batch
+    b = Batch(MEMBERS[:4], precision="fp32")
+    b.set_temporal_march(6, 2, 0)
+    th = [inputs.theta_noise(m["n"], 20 + i) for i, m in enumerate(MEMBERS[:4])]
+    for i, t in enumerate(th):
+        b.set_theta(i, t)
+    b.step(12)
+    assert list(b.status()) == [0, 0, 0, 0]
+    f, g = b.raw_state(1)
+    g[2, 9, 4] = np.inf                      # planted on the host
+    b.load_state(1, f, g)
+    b.step(24)
+    st = b.status()
+    assert st[1] != 0 and st[0] == 0 and st[2] == 0 and st[3] == 0
+    frozen = b.raw_state(1)
+    b.step(36)                               # six launches: the same copy is current again
+    after = b.raw_state(1)
+    assert np.array_equal(frozen[0], after[0], equal_nan=True)
+    assert np.array_equal(frozen[1], after[1], equal_nan=True)
+    for i in (0, 2, 3):
+        c = _single(MEMBERS[i], "fp32", th[i], 72)
+        assert np.array_equal(b.raw_state(i)[0], c.raw_state()[0]), i
+        assert np.array_equal(b.raw_state(i)[1], c.raw_state()[1]), i
+
+
 def test_sweep_shaped_batch_sampled_members():
     """The 64-cavity sweep (sides 64..512, Ra 1e3..1e5, Pr 0.001..0.01, FP32)
     in the default schedule: sampled members equal their single runs."""
