@@ -186,10 +186,11 @@ struct StepArgs {
     int tiles_x, tiles;             // tile grid of the launch
     int xcd_remap;
     Coef<real> c;
-    // Nusselt samples inside a K-step launch: for every phase j (step t + j,
-    // 1 <= j < K) whose bit is set in samp_mask, the temperature sums of the
-    // post-collision g at x = 0 and x = 1 of every row go to
-    // samp[(j - 1) * 2 n + 2 y + x] (FP64, summed as the Nusselt kernel sums)
+    // Nusselt samples taken by a K-step launch: for every step t + j
+    // (1 <= j <= K) whose bit is set in samp_mask, the temperature sums of
+    // the post-collision g at x = 0 and x = 1 of every row go to slot
+    // (number of set bits below j) of samp, samp[slot * 2 n + 2 y + x]
+    // (FP64, summed as the Nusselt kernels sum)
     double* __restrict__ samp = nullptr;
     int samp_mask = 0;
     // adjoint recompute: the linearisation point (u, v, theta planes) of
@@ -199,7 +200,7 @@ struct StepArgs {
 };
 
 // Temperature sum of a node's post-collision g in FP64, in the order the
-// Nusselt kernels use, into the sample buffer for phase j when x is 0 or 1
+// Nusselt kernels use, into the sample slot of step t + j when x is 0 or 1
 // (lanes left of the wall, x < 0, write nothing).
 template <typename real>
 __device__ __forceinline__ void samp_put(const StepArgs<real>& A, int j, int x, int y, const real (&g)[5])
@@ -208,7 +209,8 @@ __device__ __forceinline__ void samp_put(const StepArgs<real>& A, int j, int x, 
         double t = 0.0;
 #pragma unroll
         for (int i = 0; i < 5; ++i) t += double(g[i]);
-        A.samp[(j - 1) * 2 * A.n + 2 * y + x] = t;
+        const int slot = __builtin_popcount(unsigned(A.samp_mask) & ((1u << j) - 1u));
+        A.samp[(size_t)slot * 2 * A.n + 2 * y + x] = t;
     }
 }
 
@@ -936,6 +938,19 @@ __device__ __forceinline__ void stepk_tile(const StepArgs<real>& A, real* lds, i
         return;
     }
     if (!own) return;
+    if (!REC && (A.samp_mask & (1 << K))) {
+        // the last step is a Nusselt sample too
+        gather_lds<real, R>(lds, A.thw, n, x, y, lx, ly, A.c, f, g);
+        real th, ux, uy;
+        collide<real>(f, g, A.c, th, ux, uy);
+        const unsigned kb = unsigned(k) * sizeof(real), Pb = unsigned(P) * sizeof(real);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) stb(A.fout, kb + i * Pb, f[i]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) stb(A.gout, kb + i * Pb, g[i]);
+        samp_put<real>(A, K, x, y, g);
+        return;
+    }
     if constexpr (REC) {
         gather_lds<real, R>(lds, A.thw, n, x, y, lx, ly, A.c, f, g);
         real th, ux, uy;
@@ -1082,7 +1097,7 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
         real th, ux, uy;
         collide<real>(cf, cg, A.c, th, ux, uy);
         // a Nusselt sample due at this group's step: rows of this chunk only
-        if ((FIRST || w.j < K) && (A.samp_mask & (1 << w.j)) && y >= w.y0 && y < w.y1)
+        if ((A.samp_mask & (1 << w.j)) && y >= w.y0 && y < w.y1)
             samp_put<real>(A, w.j, w.x, y, cg);
     }
     __syncthreads();
@@ -1490,32 +1505,38 @@ __global__ void __launch_bounds__(256) nusselt_kernel(
     }
 }
 
-// Hot-wall Nusselt sample from the temperature sums a K-step launch wrote
-// (t[2 y] at x = 0, t[2 y + 1] at x = 1): the per-row values and the
-// reduction of nusselt_block, so the sample equals what nusselt_kernel
-// gives for that step's state; appended to the ring.
-static __global__ void __launch_bounds__(256) nusselt_samp_kernel(
-    const double* __restrict__ t, int n, const double* __restrict__ thw, double H, double inv_dT,
-    double* __restrict__ ring, unsigned long long* __restrict__ ring_count, long ring_cap)
+// Hot-wall Nusselt samples from the temperature sums that K-step launches
+// wrote into nslots consecutive slots, appended to the ring in slot order:
+// per slot the arithmetic and reduction of nusselt_block, so each sample
+// equals what nusselt_kernel gives after single steps.
+static __global__ void __launch_bounds__(256) nusselt_slots_kernel(
+    const double* __restrict__ t, int nslots, int n, const double* __restrict__ thw, double H,
+    double inv_dT, double* __restrict__ ring, unsigned long long* __restrict__ ring_count, long ring_cap)
 {
     __shared__ double part[4];
-    double acc = 0.0;
-    for (int y = threadIdx.x; y < n; y += blockDim.x) {
-        const double t0 = t[2 * y], t1 = t[2 * y + 1];
-        const double slope_in = (9.0 * t0 - t1 - 8.0 * thw[y]) * (1.0 / 3.0);
-        acc += -slope_in * H * inv_dT;
+    unsigned long long c = 0;
+    if (threadIdx.x == 0) c = *ring_count;
+    for (int sl = 0; sl < nslots; ++sl) {
+        const double* ts = t + (size_t)sl * 2 * n;
+        double acc = 0.0;
+        for (int y = threadIdx.x; y < n; y += blockDim.x) {
+            const double t0 = ts[2 * y], t1 = ts[2 * y + 1];
+            const double slope_in = (9.0 * t0 - t1 - 8.0 * thw[y]) * (1.0 / 3.0);
+            acc += -slope_in * H * inv_dT;
+        }
+        acc = wave_sum(acc);
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        if (lane == 0) part[wid] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += part[w];
+            ring[c % (unsigned long long)ring_cap] = sum / n;
+            ++c;
+        }
+        __syncthreads();                              // part is reused by the next slot
     }
-    acc = wave_sum(acc);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) part[wid] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
-        const unsigned long long c = *ring_count;
-        ring[c % (unsigned long long)ring_cap] = s / n;
-        *ring_count = c + 1;
-    }
+    if (threadIdx.x == 0) *ring_count = c;
 }
 
 // K steps per launch for the batch: tiles are footprints (origin K - 1 nodes

@@ -202,14 +202,14 @@ int launch_nusselt(dmrt_cavity* h, hipStream_t s, int copy, int wall, double* lo
                                     : launch_nusselt_t<float>(h, s, copy, wall, local, avg, to_ring);
 }
 
-// Hot-wall Nusselt sample of an intermediate step of a K-step launch, from
-// the temperature sums it wrote, appended to the ring.
-int launch_nusselt_samp(dmrt_cavity* h, hipStream_t s, int j)
+// Hot-wall Nusselt samples that K-step launches left in the first nslots
+// slots of h->samp, appended to the ring in order by one kernel.
+int launch_nusselt_slots(dmrt_cavity* h, hipStream_t s, int nslots)
 {
     const double dT = h->p.theta_hot - h->p.theta_cold;
     const double inv_dT = dT != 0.0 ? 1.0 / dT : 1.0;
-    hipLaunchKernelGGL(nusselt_samp_kernel, dim3(1), dim3(256), 0, s, h->samp + (size_t)(j - 1) * 2 * h->n,
-                       h->n, h->thw_dbl, h->d.H, inv_dT, h->ring, h->ring_count, h->ring_cap);
+    hipLaunchKernelGGL(nusselt_slots_kernel, dim3(1), dim3(256), 0, s, h->samp, nslots, h->n, h->thw_dbl,
+                       h->d.H, inv_dT, h->ring, h->ring_count, h->ring_cap);
     HIPCHK(hipGetLastError());
     return DMRT_OK;
 }
@@ -217,43 +217,60 @@ int launch_nusselt_samp(dmrt_cavity* h, hipStream_t s, int j)
 // Enqueue `count` steps starting at copy `from` with Nu samples where due;
 // `base` is the step counter before the first of them.  Groups of K =
 // h->temporal steps run as one launch through LDS when enabled; a sample
-// due inside a group is taken by that launch (the wall-column sums of the
-// step) and reduced right after it, in step order.  *flips receives the
-// number of launches (each moves the state to the other copy).
+// due at any step of a group is taken by that launch (the wall-column sums
+// of the step, into the next free slot of h->samp), and the slots are
+// reduced into the ring by one kernel when they run out and at the end, in
+// step order.  A sample after a single step is taken directly, after the
+// pending slots.  *flips receives the number of launches (each moves the
+// state to the other copy).
 int enqueue_steps(dmrt_cavity* h, hipStream_t s, int from, long base, long count, int* flips)
 {
-    int c = from, nflip = 0;
+    int c = from, nflip = 0, pend = 0;
     const int K = h->p.bc_mode == DMRT_BC_CAVITY ? h->temporal : 1;
+    auto flush = [&]() -> int {
+        if (pend == 0) return DMRT_OK;
+        const int rc = launch_nusselt_slots(h, s, pend);
+        pend = 0;
+        return rc;
+    };
     long i = 0;
     while (i < count) {
-        int mask = 0;
-        if (h->series_stride > 0)
-            for (int j = 1; j < K; ++j)
-                if ((base + i + j) % h->series_stride == 0) mask |= 1 << j;
         int rc;
         if (K >= 2 && i + K <= count) {
+            int mask = 0;
+            if (h->series_stride > 0)
+                for (int j = 1; j <= K; ++j)
+                    if ((base + i + j) % h->series_stride == 0) mask |= 1 << j;
+            const int ns = __builtin_popcount(unsigned(mask));
+            if (pend + ns > kSampSlots && (rc = flush())) return rc;
+            double* slots = h->samp ? h->samp + (size_t)pend * 2 * h->n : nullptr;
             rc = h->esz == sizeof(double)
                      ? launch_stepk<double>(h, s, fptr<double>(h, c), gptr<double>(h, c),
                                             fptr<double>(h, c ^ 1), gptr<double>(h, c ^ 1), nullptr,
-                                            nullptr, h->samp, mask)
+                                            nullptr, slots, mask)
                      : launch_stepk<float>(h, s, fptr<float>(h, c), gptr<float>(h, c),
                                            fptr<float>(h, c ^ 1), gptr<float>(h, c ^ 1), nullptr,
-                                           nullptr, h->samp, mask);
-            for (int j = 1; j < K && !rc; ++j)
-                if (mask & (1 << j)) rc = launch_nusselt_samp(h, s, j);
+                                           nullptr, slots, mask);
+            pend += ns;
             i += K;
+            if (rc) return rc;
+            c ^= 1;
+            ++nflip;
         } else {
             rc = launch_step(h, s, c);
             i += 1;
-        }
-        if (rc) return rc;
-        c ^= 1;
-        ++nflip;
-        if (h->series_stride > 0 && (base + i) % h->series_stride == 0) {
-            rc = launch_nusselt(h, s, c, 0, nullptr, nullptr, true);
             if (rc) return rc;
+            c ^= 1;
+            ++nflip;
+            if (h->series_stride > 0 && (base + i) % h->series_stride == 0) {
+                if ((rc = flush())) return rc;
+                rc = launch_nusselt(h, s, c, 0, nullptr, nullptr, true);
+                if (rc) return rc;
+            }
         }
     }
+    const int rc = flush();
+    if (rc) return rc;
     if (flips) *flips = nflip;
     return DMRT_OK;
 }
@@ -643,7 +660,7 @@ int dmrt_nu_series(dmrt_cavity* h, int stride, long cap)
     h->series_stride = stride;
     if (stride == 0) return DMRT_OK;
     if (!h->ring_count) HIPCHK(hipMalloc(&h->ring_count, sizeof(unsigned long long)));
-    if (!h->samp) HIPCHK(hipMalloc(&h->samp, (size_t)kMaxK * 2 * h->n * sizeof(double)));
+    if (!h->samp) HIPCHK(hipMalloc(&h->samp, (size_t)kSampSlots * 2 * h->n * sizeof(double)));
     HIPCHK(hipMalloc(&h->ring, cap * sizeof(double)));
     h->ring_cap = cap;
     int rc = reset_series(h);

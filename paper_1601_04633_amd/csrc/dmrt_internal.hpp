@@ -76,7 +76,7 @@ struct dmrt_cavity {
     double* res_part = nullptr;       // residual partials
     int res_blocks = 0;
     double* ring = nullptr;
-    double* samp = nullptr;           // Nusselt sample sums of K-step launches, kMaxK x 2 n doubles
+    double* samp = nullptr;           // Nusselt sample sums of K-step launches, kSampSlots x 2 n doubles
     unsigned long long* ring_count = nullptr;
     long ring_cap = 0;
     int series_stride = 0;
@@ -132,6 +132,7 @@ inline bool valid_temporal(int k, int rows)
 
 constexpr long kLdsBytes = 160 * 1024;
 constexpr int kMaxK = 6;           // most steps per launch of any K-step form
+constexpr int kSampSlots = 32;     // Nusselt sample slots reduced by one kernel (>= kMaxK)
 
 constexpr long march_lds_bytes(int k, int b, int esz)
 {
@@ -203,9 +204,9 @@ int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
 // Launches K = h->temporal steps of the cavity from (fin, gin) to (fout, gout)
 // through LDS with footprint rows h->t_rows (K >= 2).  With acc non-null the
 // launch also adds each step's hot-wall Nusselt row sums to acc (FP64, n
-// entries; thw_d the FP64 wall temperatures).  samp_mask bit j (1 <= j < K):
-// the launch writes the wall-column temperature sums of step t + j to
-// samp + (j - 1) 2 n (see StepArgs).
+// entries; thw_d the FP64 wall temperatures).  samp_mask bit j (1 <= j <= K):
+// the launch writes the wall-column temperature sums of step t + j to the
+// slot (set bits below j) of samp, 2 n doubles each (see StepArgs).
 template <typename real>
 int launch_stepk(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
                  real* gout, const double* thw_d = nullptr, double* acc = nullptr,
