@@ -198,7 +198,10 @@ int dmrt_nusselt(dmrt_cavity *h, int wall, double *nu_avg, double *nu_local);
 
 /* Record the hot-wall Nu_avg on the device every `stride` steps (counted
  * from the last initialisation), into a ring of `cap` doubles; stride 0
- * switches recording off.  Resets the ring. */
+ * switches recording off.  Resets the ring.  With K steps per launch the
+ * launches take the samples due on their steps and one small kernel per
+ * dmrt_step chunk (and per 32 samples) appends them; device memory: 64 n
+ * doubles of sample slots besides the ring. */
 int dmrt_nu_series(dmrt_cavity *h, int stride, long cap);
 
 /* Copy the recorded samples, oldest first, into out (room for cap doubles);
@@ -257,8 +260,9 @@ int dmrt_set_launch(dmrt_cavity *h, int block_x, int block_y, int xcd_remap,
  * K = 3, {10, 12, 14, 16} for K = 4.  K >= 2 is available for
  * DMRT_BC_CAVITY only (EINVAL otherwise).  Results are identical to
  * single steps; Nusselt samples are still taken after every stride-th step
- * (a sample due on an intermediate step of a launch is taken by that launch,
- * with the same value as after a single step).
+ * (a sample due on any step of a launch is taken by that launch, with the
+ * same value as after a single step, and appended to the ring, in order, by
+ * the end of the dmrt_step call's enqueued work).
  * Default at creation: K = 1.  On MI355X K = 4 with 16 rows is the fastest
  * tile shape from about 512^2 up, 12 rows below that; from 1024^2 up the
  * marching form (dmrt_set_temporal_march) is faster. */
