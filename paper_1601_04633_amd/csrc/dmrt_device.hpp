@@ -45,7 +45,9 @@ struct Coef {
     // (Eq. 30) and N (Eq. 37), negated: the moment changes come out
     // already scaled for the inverse transform
     real nsn36, nsn4, nsq12;   // -s_nu/36, -s_nu/4, -s_q/12
+    real nsn12;                // -s_nu/12: the epsilon change from a third of m8 - m8_eq
     real nsk2, nse20, nsg4;    // -sigma_k/2, -sigma_e/20, -sigma_nu/4
+    real gbh, gy0h, gxh;       // gbeta/2, gy0/2, gx/2 (exact halves): the force image uses G/2
 };
 
 // Sum over a 64-wide wavefront (FP64).
@@ -62,9 +64,12 @@ __device__ __forceinline__ double wave_sum(double v)
 // M^-1 = M^T diag(1/9, 1/6, 1/6, 1/36, 1/4, 1/4, 1/12, 1/12, 1/36) and
 // N^-1 = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4) (both matrices have orthogonal
 // rows), and only the moment changes are transformed back.  Moment order:
-// 1 j_x, 2 j_y, 3 e, 4 p_xx, 5 p_xy, 6 q_x, 7 q_y, 8 epsilon.  With GX false
-// the horizontal force is zero (the cavity, G = (0, G_y) of Eq. 27) and its
-// terms are left out.
+// 1 j_x, 2 j_y, 3 e, 4 p_xx, 5 p_xy, 6 q_x, 7 q_y, 8 epsilon.  The
+// distances of the non-conserved moments from the equilibria of Eq. 34 are
+// formed directly from the population sums: the density deviation cancels
+// from both energy moments, and q_x + u, q_y + v reduce to one term each.
+// With GX false the horizontal force is zero (the cavity, G = (0, G_y) of
+// Eq. 27) and its terms are left out.
 template <typename real, bool GX = false>
 __host__ __device__ __forceinline__ void collide(real (&f)[9], real (&g)[5], const Coef<real>& c,
                                         real& theta_out, real& ux_out, real& uy_out)
@@ -74,62 +79,56 @@ __host__ __device__ __forceinline__ void collide(real (&f)[9], real (&g)[5], con
     const real p13 = f[1] + f[3], p24 = f[2] + f[4], p57 = f[5] + f[7], p68 = f[6] + f[8];
     const real d13 = f[1] - f[3], d24 = f[2] - f[4], d57 = f[5] - f[7], d86 = f[8] - f[6];
     const real s1234 = p13 + p24, s5678 = p57 + p68;
-    const real drho = (f[0] + s1234) + s5678;
     const real w = d57 + d86, z = d57 - d86;
     const real u = d13 + w, v = d24 + z;
     const real g13 = g[1] + g[3], g24 = g[2] + g[4];
     const real gs = g13 + g24;
     const real theta = g[0] + gs;
 
-    // non-conserved moments, rows 3-8 of Eq. 30
-    const real m3 = fmr(-four, f[0], fmr(two, s5678, -s1234));
-    const real m4 = p13 - p24;
-    const real m5 = p57 - p68;
-    const real m6 = fmr(-two, d13, w);
-    const real m7 = fmr(-two, d24, z);
-    const real m8 = fmr(four, f[0], fmr(-two, s1234, s5678));
-
-    // distance from the equilibria of Eq. 34 (energy moment with the
-    // factor 3): e3 = 3|u|^2 - 2 drho, e4 = u^2 - v^2, e5 = uv,
-    // e6 = -u, e7 = -v, e8 = drho - 3|u|^2
+    // m_k - m_k^eq for rows 3-8 of Eq. 30 against Eq. 34 (energy moment
+    // with the factor 3):
+    //   r3 = e + 2 drho - 3|u|^2 = -2 f0 + s1234 + 4 s5678 - 3|u|^2
+    //   r8 = (epsilon - drho + 3|u|^2) / 3 = f0 - s1234 + |u|^2
+    //   r4 = p_xx - (u^2 - v^2), r5 = p_xy - uv
+    //   r6 = q_x + u = 2 w - d13, r7 = q_y + v = 2 z - d24
     const real uu = u * u, vv = v * v, uv = u * v;
     const real q2 = uu + vv, e4 = uu - vv;
-    const real r3 = fmr(two, drho, fmr(real(-3), q2, m3));
-    const real r8 = fmr(real(3), q2, m8 - drho);
-    const real r4 = m4 - e4, r5 = m5 - uv, r6 = m6 + u, r7 = m7 + v;
+    const real r3 = fmr(real(-3), q2, fmr(four, s5678, fmr(-two, f[0], s1234)));
+    const real r8 = (f[0] - s1234) + q2;
+    const real r4 = (p13 - p24) - e4, r5 = (p57 - p68) - uv;
+    const real r6 = fmr(two, w, -d13), r7 = fmr(two, z, -d24);
 
     // moment image of the force of Eq. 26, 3 G.(e_i - u) f_i^eq(rho0, u),
-    // divided by the squared row norms: with G = (Gx, Gy)
-    //   F3 = 3 (G.u)(2 - 3|u|^2)                    F8 = -F3
-    //   F4 = Gx u (2 - 3u^2 + 3v^2) - Gy v (2 + 3u^2 - 3v^2)
-    //   F5 = Gx v (1 - 3u^2) + Gy u (1 - 3v^2)
-    //   F6 = 6 Gy uv - Gx (1 - 3v^2)                F7 = 6 Gx uv - Gy (1 - 3u^2)
-    const real Gy = fmr(c.gbeta, theta, c.gy0);
-    const real Gv = Gy * v, Gu = Gy * u;
-    const real h3 = fmr(real(-0.25), q2, real(1.0 / 6.0));
-    const real hq = real(0.5) * uv;
+    // divided by the squared row norms, in terms of H = G / 2:
+    //   F3 = (H.u)(2/3 - |u|^2) / 2 = (H.u)(1/3 - |u|^2 / 2)      F8 = -F3
+    //   F4 = Hx u (1 - 3(u^2 - v^2)/2) - Hy v (1 + 3(u^2 - v^2)/2)
+    //   F5 = Hx v (1/2 - 3u^2/2) + Hy u (1/2 - 3v^2/2)
+    //   F6 = Hy uv + Hx (v^2/2 - 1/6)          F7 = Hx uv + Hy (u^2/2 - 1/6)
+    const real Hy = fmr(c.gbh, theta, c.gy0h);
+    const real Hv = Hy * v, Hu = Hy * u;
+    const real h3 = fmr(real(-0.5), q2, real(1.0 / 3.0));
     real F3, F4, F5, F6, F7, a1;
     if constexpr (GX) {
-        const real Gx = c.gx;
-        F3 = fmr(Gx, u, Gv) * h3;
-        F4 = fmr(Gx * u, fmr(real(-0.75), e4, real(0.5)), Gv * fmr(real(-0.75), e4, real(-0.5)));
-        F5 = fmr(Gx * v, fmr(real(-0.75), uu, real(0.25)), Gu * fmr(real(-0.75), vv, real(0.25)));
-        F6 = fmr(Gx, fmr(real(0.25), vv, real(-1.0 / 12.0)), Gy * hq);
-        F7 = fmr(Gx, hq, Gy * fmr(real(0.25), uu, real(-1.0 / 12.0)));
-        a1 = Gx * real(1.0 / 6.0);
+        const real Hx = c.gxh;
+        F3 = fmr(Hx, u, Hv) * h3;
+        F4 = fmr(Hx * u, fmr(real(-1.5), e4, real(1)), Hv * fmr(real(-1.5), e4, real(-1)));
+        F5 = fmr(Hx * v, fmr(real(-1.5), uu, real(0.5)), Hu * fmr(real(-1.5), vv, real(0.5)));
+        F6 = fmr(Hx, fmr(real(0.5), vv, real(-1.0 / 6.0)), Hy * uv);
+        F7 = fmr(Hx, uv, Hy * fmr(real(0.5), uu, real(-1.0 / 6.0)));
+        a1 = Hx * real(1.0 / 3.0);
     } else {
-        F3 = Gv * h3;
-        F4 = Gv * fmr(real(-0.75), e4, real(-0.5));
-        F5 = Gu * fmr(real(-0.75), vv, real(0.25));
-        F6 = Gy * hq;
-        F7 = Gy * fmr(real(0.25), uu, real(-1.0 / 12.0));
+        F3 = Hv * h3;
+        F4 = Hv * fmr(real(-1.5), e4, real(-1));
+        F5 = Hu * fmr(real(-1.5), vv, real(0.5));
+        F6 = Hy * uv;
+        F7 = Hy * fmr(real(0.5), uu, real(-1.0 / 6.0));
         a1 = real(0);
     }
 
     // scaled moment changes -S (m - m_eq) + F   (Eq. 28, Eq. 31)
-    const real a2 = Gy * real(1.0 / 6.0);
+    const real a2 = Hy * real(1.0 / 3.0);
     const real a3 = fmr(c.nsn36, r3, F3);
-    const real a8 = fmr(c.nsn36, r8, -F3);
+    const real a8 = fmr(c.nsn12, r8, -F3);
     const real a4 = fmr(c.nsn4, r4, F4);
     const real a5 = fmr(c.nsn4, r5, F5);
     const real a6 = fmr(c.nsq12, r6, F6);
@@ -139,14 +138,19 @@ __host__ __device__ __forceinline__ void collide(real (&f)[9], real (&g)[5], con
     const real A = fmr(-two, a8, -a3);          // f1..f4: -a3 - 2 a8
     const real D = fmr(two, a3, a8);            // f5..f8: 2 a3 + a8
     const real P = A + a4, Q = A - a4;
-    const real U1 = GX ? fmr(-two, a6, a1) : -two * a6;
     const real V1 = fmr(-two, a7, a2);
     const real X = GX ? a1 + a6 : a6;
     const real Y = a2 + a7;
     const real S = X + Y, T = Y - X, Rp = D + a5, Rm = D - a5;
     f[0] = fmr(four, a8 - a3, f[0]);
-    f[1] += P + U1;
-    f[3] += P - U1;
+    if constexpr (GX) {
+        const real U1 = fmr(-two, a6, a1);
+        f[1] += P + U1;
+        f[3] += P - U1;
+    } else {
+        f[1] = fmr(-two, a6, f[1] + P);
+        f[3] = fmr(two, a6, f[3] + P);
+    }
     f[2] += Q + V1;
     f[4] += Q - V1;
     f[5] += Rp + S;
@@ -154,17 +158,19 @@ __host__ __device__ __forceinline__ void collide(real (&f)[9], real (&g)[5], con
     f[6] += Rm + T;
     f[8] += Rm - T;
 
-    // D2Q5, Eqs. 36-42 (last row of N read as e_x^2 - e_y^2)
-    const real b1 = c.nsk2 * fmr(-u, theta, g[1] - g[3]);
-    const real b2 = c.nsk2 * fmr(-v, theta, g[2] - g[4]);
+    // D2Q5, Eqs. 36-42 (last row of N read as e_x^2 - e_y^2): with the
+    // changes b1 = -sk/2 (n1 - u theta), b2 = -sk/2 (n2 - v theta),
+    // b3 = -se/20 (n3 - a theta), b4 = -snu/4 n4,
+    // g0 -= 4 b3, g1,3 += b3 + b4 +- b1, g2,4 += b3 - b4 +- b2
     const real b3 = c.nse20 * fmr(-c.a, theta, fmr(-four, g[0], gs));
-    const real b4 = c.nsg4 * (g13 - g24);
-    const real t34 = b3 + b4, t34m = b3 - b4;
+    const real d4 = g13 - g24;
+    const real t34 = fmr(c.nsg4, d4, b3), t34m = fmr(-c.nsg4, d4, b3);
+    const real dx = fmr(-u, theta, g[1] - g[3]), dy = fmr(-v, theta, g[2] - g[4]);
     g[0] = fmr(-four, b3, g[0]);
-    g[1] += b1 + t34;
-    g[3] += t34 - b1;
-    g[2] += b2 + t34m;
-    g[4] += t34m - b2;
+    g[1] = fmr(c.nsk2, dx, g[1] + t34);
+    g[3] = fmr(-c.nsk2, dx, g[3] + t34);
+    g[2] = fmr(c.nsk2, dy, g[2] + t34m);
+    g[4] = fmr(-c.nsk2, dy, g[4] + t34m);
 
     theta_out = theta;
     ux_out = u;

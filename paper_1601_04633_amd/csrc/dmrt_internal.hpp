@@ -33,7 +33,9 @@ Coef<real> make_coef(const dmrt_params& p, const dmrt_derived& d)
     c.gx = real(p.force_x);
     c.cold = real((4.0 + d.a) / 10.0 * p.theta_cold);
     c.nsn36 = real(-d.s_nu / 36.0); c.nsn4 = real(-d.s_nu / 4.0); c.nsq12 = real(-d.s_q / 12.0);
+    c.nsn12 = real(-d.s_nu / 12.0);
     c.nsk2 = real(-d.sigma_k / 2.0); c.nse20 = real(-d.sigma_e / 20.0); c.nsg4 = real(-d.sigma_nu / 4.0);
+    c.gbh = real(d.gbeta) * real(0.5); c.gy0h = c.gy0 * real(0.5); c.gxh = c.gx * real(0.5);
     return c;
 }
 
