@@ -244,6 +244,32 @@ __device__ __forceinline__ void stb(real* __restrict__ base, unsigned b, real v)
     *reinterpret_cast<real*>(reinterpret_cast<char*>(base) + b) = v;
 }
 
+// Raw buffer access: element at byte offset voff + soff of the array at p,
+// with voff per lane (a VGPR) and soff uniform (an SGPR), so that a fixed
+// per-lane offset and a uniform row offset meet in the instruction itself.
+// Offsets stay below 4 GiB (the state's planes do, see the size limit).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(0xffffffffu), 0x00020000);
+}
+template <typename real>
+__device__ __forceinline__ real bld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    if constexpr (sizeof(real) == 4)
+        return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(real, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <typename real>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, real v)
+{
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(real) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
 // Wall temperature of row y, uniform per wave: a scalar load through the
 // constant address space, which does not wait for vector memory operations
 // in flight.
@@ -1020,19 +1046,23 @@ __global__ void __launch_bounds__(kFootW * R) stepk_rec_kernel(StepArgs<real> A)
 // end instead of at each 16-row tile, and the result equals K single-step
 // launches exactly (same gathers, same arithmetic).
 
-// Gather of node (x, y) at lane lx from the previous group's ring (14
-// planes of B + 2 rows of 64) with the cavity's wall rules, rows y - 1, y
-// and y + 1 being at slots sm, s0 and sp: every interior link from constant
-// offsets, then the wall links of lanes on a wall (as gather_lds).
+// Gather of node (x, y) from the previous group's ring (14 planes of B + 2
+// rows of 64; `ring` points at this lane's column) with the cavity's wall
+// rules, rows y - 1, y and y + 1 starting om, o0 and op elements into each
+// plane: every interior link from constant offsets, then, when `wall` (a
+// uniform flag: the wave has a lane on a side wall or the row is a bottom
+// or top row), the wall links of lanes on a wall (as gather_lds).  Every
+// read stays inside the ring for any lane, so lanes outside the band's
+// output columns may run it too.
 template <typename real, int B>
-__device__ __forceinline__ void gather_ring(const real* ring, real thw_y, int n, int x, int y, int lx,
-                                            int sm, int s0, int sp, const Coef<real>& c, real (&f)[9],
+__device__ __forceinline__ void gather_ring(const real* ring, const real* thw, bool wall, int n, int x, int y,
+                                            int om, int o0, int op, const Coef<real>& c, real (&f)[9],
                                             real (&g)[5])
 {
     constexpr int PL = (B + 2) * kFootW;
-    const real* bm = ring + (sm * kFootW + lx);   // row y - 1
-    const real* b0 = ring + (s0 * kFootW + lx);   // row y
-    const real* bp = ring + (sp * kFootW + lx);   // row y + 1
+    const real* bm = ring + om;   // row y - 1
+    const real* b0 = ring + o0;   // row y
+    const real* bp = ring + op;   // row y + 1
     f[0] = b0[0];
     f[1] = b0[1 * PL - 1];
     f[2] = bm[2 * PL];
@@ -1047,6 +1077,8 @@ __device__ __forceinline__ void gather_ring(const real* ring, real thw_y, int n,
     g[2] = bm[11 * PL];
     g[3] = b0[12 * PL + 1];
     g[4] = bp[13 * PL];
+    if (!wall) return;
+    const real thw_y = thw_row<real>(thw, y);
     const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
     if (!(hxm && hxp && hym && hyp)) {
         if (!hxm) { f[1] = b0[3 * PL]; g[1] = fmr(c.cabb, thw_y, -b0[12 * PL]); }   // Eq. 45
@@ -1060,76 +1092,166 @@ __device__ __forceinline__ void gather_ring(const real* ring, real thw_y, int n,
     }
 }
 
-// Per-wave constants of the row-marching kernel.
+// Per-wave constants of the row-marching kernel.  off[] holds per-lane byte
+// offsets that stay fixed while the wave marches: for group 1 those of the
+// nine links it gathers (march_lane_offsets), for group K those of the nine
+// planes it stores (x E + q P E); rows enter as uniform base pointers.
 template <typename real>
 struct MarchWave {
-    int j, r, x, lx, aj, aK, lo, hi, ymir, y0, y1;
-    bool xact, down;
-    const real* rin;
-    real* rout;
+    int j, x, y0, y1;
+    int ydir;            // marching row v stands for cavity row ybase + ydir v
+    int vlo, vhi;        // marching rows this group computes: its rows of the chunk, inside the cavity
+    int wallx;           // a lane of the band sits on the left or right wall
+    int samp;            // a Nusselt sample is due at this group's step
+    bool xact;           // the lane's column is one of this group's, inside the cavity
+    const real* rin;     // previous group's ring at this lane
+    real* rout;          // own ring at this lane
+    unsigned off[9];
 };
+
+// Uniform position of a wave in its sweep: marching row v, the cavity row
+// y it stands for, and the ring offsets (elements into each plane) of the
+// rows y - 1, y and y + 1, advanced by B rows per iteration.
+struct MarchPos {
+    int v, y, olo, o0, ohi;
+};
+
+// Byte offsets of the links a lane at column x (0 <= x < n) gathers in the
+// pull-stream of Eq. 25, relative to the start of the source row in plane
+// 0: row y for links 0, 1, 3, row y - 1 for 2, 5, 6 and row y + 1 for 4, 7,
+// 8.  The left and right walls are folded in: a link that would come from
+// outside reads the lane's own node in the opposite plane (halfway
+// bounce-back; the Eq. 45 temperature term is added at use), which for
+// the diagonals of the wall lanes lies one row up (links 5, 6) or down
+// (7, 8) from the source row.  The same offsets serve g (planes 0-4).
+template <typename real>
+__device__ __forceinline__ void march_lane_offsets(int x, int n, int pitch, int P, unsigned (&o)[9])
+{
+    constexpr unsigned E = sizeof(real);
+    const unsigned xe = unsigned(x) * E, Pb = unsigned(P) * E, rb = unsigned(pitch) * E;
+    const bool hxm = x > 0, hxp = x < n - 1;
+    o[0] = xe;
+    o[1] = hxm ? xe - E + Pb : xe + 3 * Pb;
+    o[2] = xe + 2 * Pb;
+    o[3] = hxp ? xe + E + 3 * Pb : xe + Pb;
+    o[4] = xe + 4 * Pb;
+    o[5] = hxm ? xe - E + 5 * Pb : xe + 7 * Pb + rb;
+    o[6] = hxp ? xe + E + 6 * Pb : xe + 8 * Pb + rb;
+    o[7] = hxp ? xe + E + 7 * Pb : xe + 5 * Pb - rb;
+    o[8] = hxm ? xe - E + 8 * Pb : xe + 6 * Pb - rb;
+}
+
+// Group 1's gather of row y (0 <= y < n) from global memory with the lane
+// offsets above: the row bases are uniform, so the loads need no per-lane
+// address arithmetic.  On the bottom and top rows (Eq. 44 walls) the links
+// that cross the wall are loaded again from the lane's own node; every
+// address stays inside the two planes' rows 0 ... n - 1.
+template <typename real>
+__device__ __forceinline__ void march_loads(const StepArgs<real>& A, const unsigned (&o)[9], int y,
+                                            real (&f)[9], real (&g)[5])
+{
+    constexpr unsigned E = sizeof(real);
+    const int n = A.n;
+    const unsigned rb = unsigned(A.pitch) * E;
+    const unsigned r0 = unsigned(y) * rb, rm = unsigned(max(y - 1, 0)) * rb, rp = unsigned(min(y + 1, n - 1)) * rb;
+    const __amdgpu_buffer_rsrc_t fr = buf_rsrc(A.fin), gr = buf_rsrc(A.gin);
+    f[0] = bld<real>(fr, o[0], r0);
+    f[1] = bld<real>(fr, o[1], r0);
+    f[2] = bld<real>(fr, o[2], rm);
+    f[3] = bld<real>(fr, o[3], r0);
+    f[4] = bld<real>(fr, o[4], rp);
+    f[5] = bld<real>(fr, o[5], rm);
+    f[6] = bld<real>(fr, o[6], rm);
+    f[7] = bld<real>(fr, o[7], rp);
+    f[8] = bld<real>(fr, o[8], rp);
+    g[0] = bld<real>(gr, o[0], r0);
+    g[1] = bld<real>(gr, o[1], r0);
+    g[2] = bld<real>(gr, o[2], rm);
+    g[3] = bld<real>(gr, o[3], r0);
+    g[4] = bld<real>(gr, o[4], rp);
+    if (y == 0 || y == n - 1) {
+        // own-node planes: o[0] + q P E
+        const unsigned Pb = unsigned(A.plane) * E;
+        if (y == 0) {                                  // Eq. 44, bottom
+            f[2] = bld<real>(fr, o[4], r0);
+            f[5] = bld<real>(fr, o[0], r0 + 7 * Pb);
+            f[6] = bld<real>(fr, o[0], r0 + 8 * Pb);
+            g[2] = bld<real>(gr, o[4], r0);
+        }
+        if (y == n - 1) {                              // Eq. 44, top
+            f[4] = bld<real>(fr, o[2], r0);
+            f[7] = bld<real>(fr, o[0], r0 + 5 * Pb);
+            f[8] = bld<real>(fr, o[0], r0 + 6 * Pb);
+            g[4] = bld<real>(gr, o[2], r0);
+        }
+    }
+}
 
 // One iteration of the row-marching kernel for the calling wave: group 1
 // computes the row gathered into (cf, cg) one iteration earlier and gathers
 // the row of its next iteration into (nf, ng) first, so that those global
 // loads stay in flight across this iteration's barriers.  The other groups
-// gather from the previous group's ring.
-template <typename real, int K, int B, bool FIRST>
-__device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchWave<real>& w, int i,
+// gather from the previous group's ring.  Whether the wave computes is
+// decided per wave (its row); all its lanes compute, and only the global
+// stores and the Nusselt sums are limited to the group's columns.
+template <typename real, int K, int B, bool FIRST, bool SAMP>
+__device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchWave<real>& w, MarchPos& p,
                                            real (&cf)[9], real (&cg)[5], real (&nf)[9], real (&ng)[5])
 {
-    constexpr int RS = B + 2, PL = RS * kFootW;
-    const int n = A.n, P = A.plane;
-    const int v = w.aj + B * i + w.r;                 // marching row, uniform per wave
-    const int y = w.down ? w.ymir - v : v;            // the cavity row it stands for
-    const int s0 = (v - w.aK) % RS;                   // ring slot of row v (v >= aK)
-    const bool act = w.xact && v >= w.lo && v < w.hi && y >= 0 && y < n;
+    constexpr int RS = B + 2, PL = RS * kFootW, RING = 14 * PL;
+    const int n = A.n, v = p.v, y = p.y;
+    const bool row = v >= w.vlo && v < w.vhi;        // uniform
     if constexpr (FIRST) {
-        // unconditional (clamped) loads: the wait for them is then placed
-        // exactly, one iteration later
-        const int xn = min(max(w.x, 0), n - 1);
-        const int yn = min(max(w.down ? w.ymir - v - B : v + B, 0), n - 1);
-        gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, P, xn, yn, nf, ng);
-        const real tw = thw_row<real>(A.thw, min(max(y, 0), n - 1));
-        if (act) gather_cavity_walls<real>(tw, n, w.x, A.c, cg);
-    } else if (act) {
-        // slots of rows v - 1 and v + 1: rows y - 1 and y + 1 when marching
-        // up, y + 1 and y - 1 when marching down
-        const int sm = s0 == 0 ? RS - 1 : s0 - 1, sp = s0 == RS - 1 ? 0 : s0 + 1;
-        gather_ring<real, B>(w.rin, thw_row<real>(A.thw, min(max(y, 0), n - 1)), n, w.x, y, w.lx,
-                             w.down ? sp : sm, s0, w.down ? sm : sp, A.c, cf, cg);
+        // unconditional loads of a clamped row: the wait for them is then
+        // placed exactly, one iteration later
+        march_loads<real>(A, w.off, min(max(y + w.ydir * B, 0), n - 1), nf, ng);
+        if (row && w.wallx) gather_cavity_walls<real>(thw_row<real>(A.thw, y), n, w.x, A.c, cg);
+    } else if (row) {
+        gather_ring<real, B>(w.rin, A.thw, w.wallx || y == 0 || y == n - 1, n, w.x, y, p.olo, p.o0, p.ohi,
+                             A.c, cf, cg);
     }
-    if (act) {
+    if (row) {
         real th, ux, uy;
         collide<real>(cf, cg, A.c, th, ux, uy);
         // a Nusselt sample due at this group's step: rows of this chunk only
-        if ((A.samp_mask & (1 << w.j)) && y >= w.y0 && y < w.y1)
-            samp_put<real>(A, w.j, w.x, y, cg);
+        if (SAMP && w.samp && y >= w.y0 && y < w.y1 && w.xact) samp_put<real>(A, w.j, w.x, y, cg);
     }
     __syncthreads();
-    if (act) {
+    // the same test once more (written differently, so that the compiler
+    // does not carry the first one across the barrier as a lane mask)
+    if (unsigned(v - w.vlo) < unsigned(w.vhi - w.vlo)) {
         if (FIRST || w.j < K) {
-            real* o = w.rout + (s0 * kFootW + w.lx);
+            // the own ring follows the previous group's: the write address
+            // is the gather's row-y address plus constants
+            real* o = FIRST ? w.rout + p.o0 : const_cast<real*>(w.rin) + p.o0 + RING;
 #pragma unroll
             for (int q = 0; q < 9; ++q) o[q * PL] = cf[q];
 #pragma unroll
             for (int q = 0; q < 5; ++q) o[(9 + q) * PL] = cg[q];
-        } else {
-            const unsigned kb = unsigned(y * A.pitch + w.x) * sizeof(real), Pb = unsigned(P) * sizeof(real);
+        } else if (w.xact) {
+            const unsigned rs = unsigned(y) * unsigned(A.pitch) * unsigned(sizeof(real));
+            const __amdgpu_buffer_rsrc_t fr = buf_rsrc(A.fout), gr = buf_rsrc(A.gout);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) stb(A.fout, kb + q * Pb, cf[q]);
+            for (int q = 0; q < 9; ++q) bst<real>(fr, w.off[q], rs, cf[q]);
 #pragma unroll
-            for (int q = 0; q < 5; ++q) stb(A.gout, kb + q * Pb, cg[q]);
+            for (int q = 0; q < 5; ++q) bst<real>(gr, w.off[q], rs, cg[q]);
         }
     }
     __syncthreads();
+    // next row: B further, each ring slot B further round the ring
+    constexpr int STEP = B * kFootW, WRAP = RS * kFootW;
+    p.v = v + B;
+    p.y = y + w.ydir * B;
+    p.olo = p.olo + STEP >= WRAP ? p.olo + STEP - WRAP : p.olo + STEP;
+    p.o0 = p.o0 + STEP >= WRAP ? p.o0 + STEP - WRAP : p.o0 + STEP;
+    p.ohi = p.ohi + STEP >= WRAP ? p.ohi + STEP - WRAP : p.ohi + STEP;
 }
 
 // One workgroup's sweep: the column band whose footprint starts at column
 // x_band (64 lanes, output columns x_band + K - 1 ... x_band + 64 - K) over
 // the chunk of rows [y0, y1), marching down the rows when `down`; lds holds
 // the K - 1 rings of 14 planes x (B + 2) rows x 64.
-template <typename real, int K, int B>
+template <typename real, int K, int B, bool SAMP = false>
 __device__ __forceinline__ void stepm_sweep(const StepArgs<real>& A, real* lds, int x_band, int y0, int y1,
                                             bool down)
 {
@@ -1137,42 +1259,60 @@ __device__ __forceinline__ void stepm_sweep(const StepArgs<real>& A, real* lds, 
     MarchWave<real> w;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);   // blockDim.x = 64: one wave per y index
     w.j = wv / B + 1;
-    w.r = wv - (w.j - 1) * B;
-    w.lx = threadIdx.x;
-    w.x = x_band + w.lx;
+    const int r = wv - (w.j - 1) * B;
+    const int lx = threadIdx.x;
+    w.x = x_band + lx;
     const int n = A.n;
     const int a1 = y0 - (K - 1);
-    w.aj = a1 - (w.j - 1) * (B + 1);
-    w.aK = a1 - (K - 1) * (B + 1);
-    const int T = (y1 - 1 - w.aK) / B + 1;            // iterations until group K has passed y1 - 1
-    w.lo = y0 - (K - w.j);
-    w.hi = y1 + (K - w.j);
-    w.down = down;
-    w.ymir = y0 + y1 - 1;
+    const int aj = a1 - (w.j - 1) * (B + 1);
+    const int aK = a1 - (K - 1) * (B + 1);
+    const int T = (y1 - 1 - aK) / B + 1;              // iterations until group K has passed y1 - 1
+    const int ybase = down ? y0 + y1 - 1 : 0;
+    w.ydir = down ? -1 : 1;
+    // group j computes the marching rows [y0 - (K - j), y1 + (K - j)) whose
+    // cavity rows lie in [0, n)
+    w.vlo = max(y0 - (K - w.j), down ? ybase - n + 1 : 0);
+    w.vhi = min(y1 + (K - w.j), down ? ybase + 1 : n);
+    w.wallx = (x_band <= 0 && x_band + kFootW > 0) || (x_band <= n - 1 && x_band + kFootW > n - 1);
+    w.samp = (A.samp_mask >> w.j) & 1;
     w.y0 = y0;
     w.y1 = y1;
-    w.xact = w.x >= 0 && w.x < n && w.lx >= w.j - 1 && w.lx <= kFootW - w.j;
-    w.rin = lds + (w.j >= 2 ? (w.j - 2) * RING : 0);
-    w.rout = lds + (w.j < K ? (w.j - 1) * RING : 0);
+    w.xact = w.x >= 0 && w.x < n && lx >= w.j - 1 && lx <= kFootW - w.j;
+    w.rin = lds + (w.j >= 2 ? (w.j - 2) * RING : 0) + lx;
+    w.rout = lds + (w.j < K ? (w.j - 1) * RING : 0) + lx;
+    const int xn = min(max(w.x, 0), n - 1);           // lanes outside the cavity gather a clamped column
+    if (w.j == 1) {
+        march_lane_offsets<real>(xn, n, A.pitch, A.plane, w.off);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) w.off[q] = (unsigned(xn) + unsigned(q) * unsigned(A.plane)) * sizeof(real);
+    }
+    // first row, and the ring slots of its rows y - 1, y, y + 1 (marching
+    // rows v - ydir, v, v + ydir; row v sits in slot (v - aK) mod (B + 2))
+    MarchPos p;
+    p.v = aj + r;
+    p.y = ybase + w.ydir * p.v;
+    const int s0 = (p.v - aK) % RS;
+    p.o0 = s0 * kFootW;
+    p.olo = ((s0 + RS - w.ydir) % RS) * kFootW;
+    p.ohi = ((s0 + RS + w.ydir) % RS) * kFootW;
     real af[9], ag[5], bf[9], bg[5];
-    if (w.j == 1)
-        gather_cavity_loads<real>(A.fin, A.gin, n, A.pitch, A.plane, min(max(w.x, 0), n - 1),
-                                  min(max(w.down ? w.ymir - w.aj - w.r : w.aj + w.r, 0), n - 1), af, ag);
+    if (w.j == 1) march_loads<real>(A, w.off, min(max(p.y, 0), n - 1), af, ag);
     // group 1 and the others run separate loops (the same number of
     // barriers each); two iterations per trip with the roles of the two
     // register sets swapped, so the prefetched values need no copies
     if (w.j == 1) {
         for (int i = 0; i < T; i += 2) {
-            march_iter<real, K, B, true>(A, w, i, af, ag, bf, bg);
-            if (i + 1 < T) march_iter<real, K, B, true>(A, w, i + 1, bf, bg, af, ag);
+            march_iter<real, K, B, true, SAMP>(A, w, p, af, ag, bf, bg);
+            if (i + 1 < T) march_iter<real, K, B, true, SAMP>(A, w, p, bf, bg, af, ag);
         }
     } else {
-        for (int i = 0; i < T; ++i) march_iter<real, K, B, false>(A, w, i, af, ag, bf, bg);
+        for (int i = 0; i < T; ++i) march_iter<real, K, B, false, SAMP>(A, w, p, af, ag, bf, bg);
     }
 }
 
-template <typename real, int K, int B>
-__global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A, int chunk)
+template <typename real, int K, int B, bool SAMP>
+__device__ __forceinline__ void stepm_body(const StepArgs<real>& A, int chunk)
 {
     constexpr int RS = B + 2, W = kFootW - 2 * (K - 1), RING = 14 * RS * kFootW;
     static_assert(K >= 2 && W > 0, "K out of range");
@@ -1185,7 +1325,20 @@ __global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A,
     // odd chunks march down (row y0 + y1 - 1 - v for marching row v), so
     // that two neighbouring chunks read the rows they share at the same
     // time, at the end of both sweeps or at the start of both
-    stepm_sweep<real, K, B>(A, lds, txt * W - (K - 1), y0, min(y0 + chunk, A.n), (tyt & 1) != 0);
+    stepm_sweep<real, K, B, SAMP>(A, lds, txt * W - (K - 1), y0, min(y0 + chunk, A.n), (tyt & 1) != 0);
+}
+
+template <typename real, int K, int B>
+__global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A, int chunk)
+{
+    stepm_body<real, K, B, false>(A, chunk);
+}
+
+// The same with Nusselt samples taken in the launch (samp_mask non-zero).
+template <typename real, int K, int B>
+__global__ void __launch_bounds__(kFootW * K * B) stepm_samp_kernel(StepArgs<real> A, int chunk)
+{
+    stepm_body<real, K, B, true>(A, chunk);
 }
 
 // lambda at footprint node (lx, ly) from mu of the previous phase in LDS:

@@ -195,7 +195,10 @@ int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
 #define DMRT_KB(KK, BB)                                                                  \
     if constexpr (march_lds_bytes(KK, BB, sizeof(real)) <= kLdsBytes)                     \
         if (K == KK && B == BB) {                                                         \
-            hipLaunchKernelGGL((stepm_kernel<real, KK, BB>), grid, block, 0, s, A, chunk);  \
+            if (samp_mask)                                                                \
+                hipLaunchKernelGGL((stepm_samp_kernel<real, KK, BB>), grid, block, 0, s, A, chunk); \
+            else                                                                          \
+                hipLaunchKernelGGL((stepm_kernel<real, KK, BB>), grid, block, 0, s, A, chunk); \
             return record_hip(hipGetLastError(), "stepm_kernel");                        \
         }
     DMRT_FOR_EACH_KB(DMRT_KB)
