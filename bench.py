@@ -35,11 +35,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD published)
 # (614.4 G wave instructions/s; 78.6 TFLOP/s if every one were an FMA).
 VALU_PEAK_GINSTR = 256 * 4 * 2.4 / 4
 WORDS_PER_NODE = 28            # 14 populations read + 14 written per node and launch
-# Algorithmic arithmetic of a node update: the 112 floating-point
-# instructions of the collision (moments, equilibria, force image,
-# relaxation and back-transform; streaming is data movement), i.e. 112 wave
-# instructions per 64 node updates.
-ALG_VALU_PER_NODE = 112
+# Algorithmic arithmetic of a node update: the 100 floating-point
+# instructions of the collision (moments, equilibrium distances, force
+# image, relaxation and back-transform; streaming is data movement), i.e.
+# 100 wave instructions per 64 node updates.
+ALG_VALU_PER_NODE = 100
 # committed counter summaries, by (kernel, cavity side)
 TRAFFIC_FILES = {
     ("step_kernel<float, 0>", 1024): "step_kernel_cavity_1024_fp32_traffic.json",
