@@ -45,14 +45,15 @@ TRAFFIC_FILES = {
     ("step_kernel<float, 0>", 1024): "step_kernel_cavity_1024_fp32_traffic.json",
     ("stepk_kernel<float, 16, 4>", 1024): "stepk_kernel_K4_R16_cavity_1024_fp32_traffic.json",
     ("stepm_kernel<float, 4, 3>", 1024): "stepm_kernel_K4_B3_cavity_1024_fp32_traffic.json",
+    ("stepm_kernel<float, 6, 2>", 1024): "stepm_kernel_K6_B2_cavity_1024_fp32_traffic.json",
     ("stepm_kernel<float, 6, 2>", 2048): "stepm_kernel_K6_B2_cavity_2048_fp32_traffic.json",
     ("stepm_kernel<double, 4, 4>", 1024): "stepm_kernel_K4_B4_cavity_1024_fp64_traffic.json",
 }
 # launch configuration timed by default (the fastest for this workload on
-# MI355X): four steps per launch, workgroups of 4 x 3 wavefronts marching
+# MI355X): six steps per launch, workgroups of 6 x 2 wavefronts marching
 # up chunks of rows (chunk length chosen to keep one launch resident),
 # die-aware order, graphs of 60 steps
-DEFAULT_TEMPORAL = ("march", 4, 3, 0)
+DEFAULT_TEMPORAL = ("march", 6, 2, 0)
 DEFAULT_LAUNCH = (256, 1, 1, 60)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_04633_amd", "csrc", f)
                   for f in ("dmrt_device.hpp",)]
@@ -374,7 +375,8 @@ def bench_adjoint(n=256, Ra=1e4, Pr=0.01, N=10000, K=2000, C=500, precision="fp3
             "backward_us_per_step": round(t_bwd / N * 1e6, 3),
             "backward_over_forward": round(t_bwd / t_plain, 3),
             "forward_plus_backward_over_forward": round((t_fwd + t_bwd) / t_plain, 3),
-            "backward_over_forward_bytes": round(adjoint_words(int(bwd[0])) / (28 / int(best["temporal"][0])), 3),
+            "backward_over_forward_bytes": round(adjoint_words(int(bwd[0]))
+                                                 / (28 / steps_per_launch(tuple(best["temporal"]))), 3),
             "roofline": adjoint_roofline(n, t_bwd / N, int(bwd[0]), 8 if precision == "fp64" else 4),
             "J": J, "grad_theta_w_norm": float(np.linalg.norm(gw)),
             "grad_theta0_norm": float(np.linalg.norm(g0))}
@@ -535,6 +537,8 @@ def main():
             extras[name] = {"mlups": round(m, 1),
                             "roofline": roofline(kn, e, n_, k, ms_step_ * k * 1e3, counter_summary(kn, n_))}
 
+        log("extra: fp32 row-marching with four steps per launch (4 x 3 wavefronts)")
+        extra("fp32_march_K4_B3", n, prec, max(args.steps // 5, 2000), 500, ("march", 4, 3, 0))
         log("extra: fp64 same cavity, row-marching (4 steps, 4 x 4 wavefronts) and tile (4 steps, 16 rows)")
         extra("fp64_march_K4_B4", n, "fp64", max(args.steps // 10, 1200), 600, ("march", 4, 4, 0))
         extra("fp64_tile_K4_R16", n, "fp64", max(args.steps // 10, 1200), 600, (4, 16))

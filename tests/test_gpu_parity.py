@@ -126,11 +126,14 @@ def test_config0_fp64_20000_steps(oracle_mod):
 
 
 def _set_mode(c, mode):
-    """The benchmark's launch shape (four steps per launch, workgroups of
-    4 x 3 wavefronts marching up chunks of rows) or the tile form (64 x 16
-    footprints); die-aware order and graphs of 60 steps in both."""
+    """The benchmark's launch shape (six steps per launch, workgroups of
+    6 x 2 wavefronts marching up chunks of rows), the four-step marching
+    form (4 x 3 wavefronts) or the tile form (64 x 16 footprints);
+    die-aware order and graphs of 60 steps in all."""
     c.set_launch(256, 1, 1, 60)
-    if mode == "march":
+    if mode == "march6":
+        c.set_temporal_march(6, 2, 0)
+    elif mode == "march":
         c.set_temporal_march(4, 3, 0)
     else:
         c.set_temporal(4, 16)
@@ -147,12 +150,13 @@ def oracle_1024(oracle_mod):
     return o.fields(), o.nusselt(0)[0]
 
 
-@pytest.mark.parametrize("mode", ["march", "tile"])
+@pytest.mark.parametrize("mode", ["march6", "march", "tile"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_full_size_1024_matches_oracle(oracle_1024, precision, tol, mode):
     """1024^2, Ra 1e5, Pr 0.001 in the benchmark's launch shape (and the
-    tile form): U, V, theta, P and the hot-wall Nu after 52 steps (13
-    four-step launches, a graph of 60 steps not yet reached) within the
+    four-step marching and tile forms): U, V, theta, P and the hot-wall Nu
+    after 52 steps (eight six-step launches and a remainder, or 13
+    four-step launches; a graph of 60 steps not yet reached) within the
     precision's bar of the oracle."""
     from paper_1601_04633_amd.dmrt import Cavity
     print(f"[parity] 1024^2 {precision} {mode}", flush=True)
@@ -175,9 +179,9 @@ def test_full_size_1024_matches_oracle(oracle_1024, precision, tol, mode):
 @pytest.mark.parametrize("n,temporal", [(1024, ("march", 4, 3, 0)), (1024, ("tile", 4, 16)),
                                         (1024, ("march", 6, 2, 0)), (2048, ("march", 6, 2, 0))])
 def test_full_size_multi_step_equals_single_steps(precision, n, temporal):
-    """The benchmark's launch shapes at full size (four steps per launch on
-    marching workgroups with the automatic chunk, the tile form, and six
-    steps per launch), 4,000 steps (1,200 at 2048^2) from theta noise of
+    """The launch shapes at full size (six steps per launch on marching
+    workgroups with the automatic chunk — the benchmark's —, four steps per
+    launch marching and in tiles), 4,000 steps (1,200 at 2048^2) from theta noise of
     amplitude 1e-2: bitwise the state of one step per launch."""
     from paper_1601_04633_amd.dmrt import Cavity
     steps = 4000 if n == 1024 else 1200
@@ -559,12 +563,13 @@ def test_marching_rejects_bad_arguments():
     p.close()
 
 
-@pytest.mark.parametrize("mode", ["march", "tile"])
+@pytest.mark.parametrize("mode", ["march6", "march", "tile"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_full_size_centro_symmetry_in_benchmark_shape(precision, mode):
     """1024^2, Ra 1e5, Pr 0.001 in the benchmark's launch shape (and the
-    tile form), 4,000 steps from theta = 0: rotating the cavity by 180
-    degrees and flipping theta maps the problem onto itself, so theta, U, V
+    four-step marching and tile forms), 4,000 steps from theta = 0:
+    rotating the cavity by 180 degrees and flipping theta maps the problem
+    onto itself, so theta, U, V
     stay antisymmetric and P symmetric at full size (a property that holds
     at any size, where the oracle cannot follow)."""
     from paper_1601_04633_amd.dmrt import Cavity
