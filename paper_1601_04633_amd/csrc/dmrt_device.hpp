@@ -1823,14 +1823,17 @@ __global__ void __launch_bounds__(256) batch_check_kernel(const CavityDev<real>*
 // Watchdog of dmrt_step: the populations of the two isothermal-wall columns
 // (x = 0 and x = n - 1, all 14 planes).  A non-finite value anywhere in the
 // cavity reaches one of them within n steps (information moves one node per
-// step).  One workgroup; sets *flag (pinned host memory) when one is found.
+// step).  One thread per wall node (grid of ceil(2n / 256) workgroups), so
+// the check costs about one memory latency; sets *flag (pinned host memory)
+// when one is found.
 template <typename real>
 __global__ void __launch_bounds__(256) wall_check_kernel(const real* __restrict__ fs,
                                                          const real* __restrict__ gs, int n, int pitch,
                                                          int plane, int* __restrict__ flag)
 {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     int bad = 0;
-    for (int t = threadIdx.x; t < 2 * n; t += blockDim.x) {
+    if (t < 2 * n) {
         const int y = t >> 1, x = (t & 1) ? n - 1 : 0;
         const int k = y * pitch + x;
         real s = real(0);
@@ -1838,7 +1841,7 @@ __global__ void __launch_bounds__(256) wall_check_kernel(const real* __restrict_
         for (int i = 0; i < 9; ++i) s += fabs(fs[i * plane + k]);
 #pragma unroll
         for (int i = 0; i < 5; ++i) s += fabs(gs[i * plane + k]);
-        bad |= !isfinite(s);
+        bad = !isfinite(s);
     }
     bad = __syncthreads_or(bad);
     if (threadIdx.x == 0 && bad) *flag = 1;

@@ -223,10 +223,72 @@ int launch_nusselt_slots(dmrt_cavity* h, hipStream_t s, int nslots)
 // step order.  A sample after a single step is taken directly, after the
 // pending slots.  *flips receives the number of launches (each moves the
 // state to the other copy).
+//
+// With the marching form, a count that is not a multiple of K ends in
+// marching launches of fewer steps where the kernel has such shapes (the
+// last K + r or r steps split into the fewest of them), and only what is
+// left in single steps; every form computes the same arithmetic, so the
+// state is bitwise the same.
+namespace {
+// Launch sizes, from the set `sz` (at most kMaxK each), that add up to
+// `total` <= 2 kMaxK: the fewest launches, and of those the one whose
+// smallest launch is largest (short launches are the least efficient per
+// step); empty if there is none.
+void split_rec(int left, int maxk, const std::vector<int>& sz, std::vector<int>& cur, std::vector<int>& best)
+{
+    if (left == 0) {
+        const bool better = best.empty() || cur.size() < best.size() ||
+                            (cur.size() == best.size() && cur.back() > best.back());
+        if (better) best = cur;
+        return;
+    }
+    if (!best.empty() && cur.size() >= best.size()) return;
+    for (int k : sz)
+        if (k <= left && k <= maxk) {   // non-increasing sizes: each multiset once
+            cur.push_back(k);
+            split_rec(left - k, k, sz, cur, best);
+            cur.pop_back();
+        }
+}
+std::vector<int> split_steps(int total, std::vector<int> sz)
+{
+    std::sort(sz.rbegin(), sz.rend());
+    std::vector<int> cur, best;
+    split_rec(total, total, sz, cur, best);
+    return best;
+}
+}  // namespace
+
 int enqueue_steps(dmrt_cavity* h, hipStream_t s, int from, long base, long count, int* flips)
 {
     int c = from, nflip = 0, pend = 0;
     const int K = h->p.bc_mode == DMRT_BC_CAVITY ? h->temporal : 1;
+    // launch sizes of the whole count: full K-step launches, the tail's
+    // multi-step launches, then single steps
+    long full = K >= 2 ? count / K : 0, singles = count - full * K;
+    std::vector<int> tail;
+    if (K >= 2 && singles > 0 && h->march) {
+        std::vector<int> sz{K};
+        for (int k = 2; k < K; ++k)
+            if (h->march_rem_B[k]) sz.push_back(k);
+        // the tail of r steps alone, or with the last full launch (the
+        // fewer launches in all, then the larger smallest launch)
+        const int r = int(singles);
+        tail = split_steps(r, sz);
+        if (full > 0) {
+            std::vector<int> t2 = split_steps(K + r, sz);
+            const bool better = !t2.empty() &&
+                                (tail.empty() || t2.size() < tail.size() + 1 ||
+                                 (t2.size() == tail.size() + 1 && t2.back() > tail.back()));
+            if (better) {
+                tail = t2;
+                --full;
+            }
+        }
+        if (!tail.empty()) singles = 0;
+    }
+    long launch = 0;
+    const long nlaunch = full + long(tail.size()) + singles;
     auto flush = [&]() -> int {
         if (pend == 0) return DMRT_OK;
         const int rc = launch_nusselt_slots(h, s, pend);
@@ -234,25 +296,34 @@ int enqueue_steps(dmrt_cavity* h, hipStream_t s, int from, long base, long count
         return rc;
     };
     long i = 0;
-    while (i < count) {
+    for (; launch < nlaunch; ++launch) {
         int rc;
-        if (K >= 2 && i + K <= count) {
+        const long t = launch - full;
+        const int m = t < 0 ? K : (t < long(tail.size()) ? tail[size_t(t)] : 1);
+        if (m >= 2) {
             int mask = 0;
             if (h->series_stride > 0)
-                for (int j = 1; j <= K; ++j)
+                for (int j = 1; j <= m; ++j)
                     if ((base + i + j) % h->series_stride == 0) mask |= 1 << j;
             const int ns = __builtin_popcount(unsigned(mask));
             if (pend + ns > kSampSlots && (rc = flush())) return rc;
             double* slots = h->samp ? h->samp + (size_t)pend * 2 * h->n : nullptr;
-            rc = h->esz == sizeof(double)
-                     ? launch_stepk<double>(h, s, fptr<double>(h, c), gptr<double>(h, c),
-                                            fptr<double>(h, c ^ 1), gptr<double>(h, c ^ 1), nullptr,
-                                            nullptr, slots, mask)
-                     : launch_stepk<float>(h, s, fptr<float>(h, c), gptr<float>(h, c),
-                                           fptr<float>(h, c ^ 1), gptr<float>(h, c ^ 1), nullptr,
-                                           nullptr, slots, mask);
+            if (m == K)
+                rc = h->esz == sizeof(double)
+                         ? launch_stepk<double>(h, s, fptr<double>(h, c), gptr<double>(h, c),
+                                                fptr<double>(h, c ^ 1), gptr<double>(h, c ^ 1), nullptr,
+                                                nullptr, slots, mask)
+                         : launch_stepk<float>(h, s, fptr<float>(h, c), gptr<float>(h, c),
+                                               fptr<float>(h, c ^ 1), gptr<float>(h, c ^ 1), nullptr,
+                                               nullptr, slots, mask);
+            else
+                rc = h->esz == sizeof(double)
+                         ? launch_stepm<double>(h, s, fptr<double>(h, c), gptr<double>(h, c),
+                                                fptr<double>(h, c ^ 1), gptr<double>(h, c ^ 1), slots, mask, m)
+                         : launch_stepm<float>(h, s, fptr<float>(h, c), gptr<float>(h, c),
+                                               fptr<float>(h, c ^ 1), gptr<float>(h, c ^ 1), slots, mask, m);
             pend += ns;
-            i += K;
+            i += m;
             if (rc) return rc;
             c ^= 1;
             ++nflip;
@@ -530,13 +601,14 @@ int dmrt_set_hot_wall(dmrt_cavity* h, const double* theta_w)
 
 static int launch_wall_check(dmrt_cavity* h)
 {
+    const dim3 grid((2 * h->n + 255) / 256);
     if (h->esz == sizeof(double))
-        hipLaunchKernelGGL((wall_check_kernel<double>), dim3(1), dim3(256), 0, h->stream,
+        hipLaunchKernelGGL((wall_check_kernel<double>), grid, dim3(256), 0, h->stream,
                            static_cast<const double*>(h->fbuf) + (size_t)h->cur * 9 * h->plane,
                            static_cast<const double*>(h->gbuf) + (size_t)h->cur * 5 * h->plane, h->n,
                            h->pitch, h->plane, const_cast<int*>(h->nonfinite));
     else
-        hipLaunchKernelGGL((wall_check_kernel<float>), dim3(1), dim3(256), 0, h->stream,
+        hipLaunchKernelGGL((wall_check_kernel<float>), grid, dim3(256), 0, h->stream,
                            static_cast<const float*>(h->fbuf) + (size_t)h->cur * 9 * h->plane,
                            static_cast<const float*>(h->gbuf) + (size_t)h->cur * 5 * h->plane, h->n,
                            h->pitch, h->plane, const_cast<int*>(h->nonfinite));
@@ -850,6 +922,22 @@ int dmrt_set_temporal_march(dmrt_cavity* h, int steps_per_launch, int group_rows
     if (steps_per_launch <= 4 && !valid_temporal(steps_per_launch, h->t_rows)) h->t_rows = 10;
     h->march = group_rows;
     h->march_chunk = std::min(chunk, h->n);
+    // shapes for the launches of fewer steps that end a count (the same
+    // wave rows per group where the kernel has them, else the most)
+    for (int k = 0; k < 8; ++k) h->march_rem_B[k] = h->march_rem_chunk[k] = 0;
+    for (int k = 2; k < steps_per_launch; ++k) {
+        int bk = valid_march(k, group_rows, int(h->esz)) ? group_rows : 0;
+        for (int b = 8; b >= 1 && !bk; --b)
+            if (valid_march(k, b, int(h->esz))) bk = b;
+        if (!bk) continue;
+        int ck = chunk_rows;
+        if (ck == 0)
+            ck = h->esz == sizeof(double) ? march_chunk_auto<double>(h->n, k, bk, h->dev)
+                                          : march_chunk_auto<float>(h->n, k, bk, h->dev);
+        if (ck <= 0) continue;
+        h->march_rem_B[k] = bk;
+        h->march_rem_chunk[k] = std::min(ck, h->n);
+    }
     return DMRT_OK;
 }
 

@@ -87,6 +87,9 @@ struct dmrt_cavity {
     int temporal = 1, t_rows = 10;    // steps per launch (1, or 2..4 through LDS) and its tile rows
     int march = 0, march_chunk = 0;   // K-step launches marching up the rows: wave rows per step
                                       // group (0: off) and rows per workgroup
+    // marching launches of fewer steps that end a count which is not a
+    // multiple of K: wave rows per group (0: none) and chunk rows, by steps
+    int march_rem_B[8] = {}, march_rem_chunk[8] = {};   // indexed by steps, up to kMaxK
     int adj_temporal = 1, adj_rows = 10;   // the same for the adjoint's backward launches
     int graph_flips[2] = {0, 0};      // copy changes made by one replay of graph[p]
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -134,6 +137,7 @@ inline bool valid_temporal(int k, int rows)
 
 constexpr long kLdsBytes = 160 * 1024;
 constexpr int kMaxK = 6;           // most steps per launch of any K-step form
+static_assert(kMaxK < 8, "dmrt_cavity::march_rem_B holds steps up to 7");
 constexpr int kSampSlots = 32;     // Nusselt sample slots reduced by one kernel (>= kMaxK)
 
 constexpr long march_lds_bytes(int k, int b, int esz)
@@ -173,12 +177,15 @@ int march_chunk_auto(int n, int K, int B, int dev)
 }
 
 // Launches K = h->temporal steps of the cavity with the row-marching kernel
-// (h->march wave rows per step group, h->march_chunk rows per workgroup).
+// (h->march wave rows per step group, h->march_chunk rows per workgroup),
+// or k < K steps in the shape of h->march_rem_B[k] and h->march_rem_chunk[k].
 template <typename real>
 int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const real* gin, real* fout,
-                 real* gout, double* samp = nullptr, int samp_mask = 0)
+                 real* gout, double* samp = nullptr, int samp_mask = 0, int k = 0)
 {
-    const int K = h->temporal, B = h->march, chunk = h->march_chunk;
+    const bool rem = k > 0 && k != h->temporal;
+    const int K = rem ? k : h->temporal, B = rem ? h->march_rem_B[k] : h->march;
+    const int chunk = rem ? h->march_rem_chunk[k] : h->march_chunk;
     StepArgs<real> A;
     A.fin = fin; A.gin = gin; A.fout = fout; A.gout = gout;
     A.samp = samp; A.samp_mask = samp_mask;

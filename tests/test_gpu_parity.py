@@ -522,6 +522,37 @@ def test_nu_series_inside_multi_step_launches(precision, temporal):
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("temporal", [("march", 6, 2, 0), ("march", 4, 3, 0), ("march", 4, 2, 11)])
+def test_step_counts_not_multiple_of_k(precision, temporal):
+    """Counts that are not a multiple of K end in marching launches of fewer
+    steps (e.g. 20 = 6 + 6 + 4 + 4 for K = 6): every count from 1 to 13, then
+    17 and 20, called one after another, gives bitwise the state and the
+    Nusselt series (a sample every 3 steps) of single steps, without graphs
+    so that each call plans its own launches."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    n = 100
+    th0 = inputs.theta_noise(n, 91, amp=1e-2)
+    counts = list(range(1, 14)) + [17, 20]
+    print(f"[parity] step counts {counts} in {temporal} {precision}", flush=True)
+    out = []
+    for mode in (None, temporal):
+        c = Cavity(n=n, Ra=2e4, Pr=0.01, precision=precision)
+        if mode:
+            c.set_temporal_march(*mode[1:])
+        c.set_launch(256, 1, 1, 0)
+        c.set_theta(th0)
+        c.nu_series(3, 100)
+        for k in counts:
+            c.step(k)
+        out.append((c.nu_series_read(), c.raw_state()))
+        c.close()
+    (sa, (fa, ga)), (sb, (fb, gb)) = out
+    assert len(sa) == sum(counts) // 3
+    np.testing.assert_array_equal(sa, sb)
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
 def test_marching_fp64_matches_oracle(oracle_mod):
     o, c = _pair(oracle_mod, 100, 1e4, 0.01)
     c.set_temporal_march(4, 4, 0)
