@@ -180,21 +180,21 @@ def apply_temporal(c, temporal):
     return None
 
 
-def device_warmup(ms=250.0):
+def device_warmup(ms=100.0):
     """Keeps the GPU busy for about `ms` milliseconds with work unrelated to
-    the cavity (FP32 products of two 4096 x 4096 matrices), so that a short
-    timed region does not start at idle clocks; returns the time spent."""
+    the cavity (an elementwise sine over a 16 MB buffer, vector-ALU bound and
+    cache resident), so that a short timed region does not start at idle
+    clocks; returns the time spent."""
     import torch
-    a = torch.randn(4096, 4096, device="cuda")
-    b = torch.randn(4096, 4096, device="cuda")
+    x = torch.rand(4 << 20, device="cuda")
     torch.cuda.synchronize()
     t = time.perf_counter()
     while (time.perf_counter() - t) * 1e3 < ms:
-        for _ in range(8):
-            a = torch.mm(a, b).mul_(1.0 / 4096)
+        for _ in range(16):
+            torch.sin(x, out=x)
         torch.cuda.synchronize()
     spent = (time.perf_counter() - t) * 1e3
-    del a, b
+    del x
     return spent
 
 
@@ -462,7 +462,7 @@ def main():
     ap.add_argument("--Pr", type=float, default=0.001)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--device-warmup-ms", type=float, default=250.0,
+    ap.add_argument("--device-warmup-ms", type=float, default=100.0,
                     help="untimed device work (not cavity steps) before the warm-up steps of the main timing")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,xcd_remap,graph_steps")
@@ -531,7 +531,7 @@ def main():
                        "chunk_rows": info.get("chunk_rows")} if temporal[0] == "march"
                       else {"kernel": "tile", "tile_rows": temporal[1]})},
         "nu_hot_wall": nu,
-        # untimed: matrix products on the device right before the warm-up
+        # untimed: elementwise work on the device right before the warm-up
         # steps (clocks at their working level for a short timed region)
         "device_warmup_ms": info.get("device_warmup_ms", 0.0),
     }

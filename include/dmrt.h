@@ -168,17 +168,20 @@ int dmrt_set_hot_wall(dmrt_cavity *h, const double *theta_w);
 
 /* Advance nsteps >= 0 time steps (Eqs. 25 and 36 with the walls).  Enqueued
  * only; long runs replay a captured graph of the step kernel.  Each call
- * with nsteps > 0 ends with a watchdog check of the populations of the two
- * isothermal-wall columns (a non-finite value anywhere reaches one of them
- * within n steps).  When a check of an earlier call has found a non-finite
- * value, dmrt_step returns DMRT_ENONFINITE and enqueues nothing; the report
- * is asynchronous (it may come one call late, or at dmrt_sync).
+ * with nsteps > 0 runs a watchdog check of the populations of the two
+ * isothermal-wall columns of the state it starts from (a non-finite value
+ * anywhere reaches one of them within n steps), in extra workgroups of its
+ * first launch, or as a launch of its own when the call starts with a graph
+ * replay.  When a check has found a non-finite value, dmrt_step returns
+ * DMRT_ENONFINITE and enqueues nothing; the report is asynchronous (it comes
+ * from a later call once the check has run, or from dmrt_sync).
  * dmrt_set_theta, dmrt_set_equilibrium and dmrt_load_state clear it. */
 int dmrt_step(dmrt_cavity *h, long nsteps);
 
-/* Wait for all work enqueued on the handle's stream.  Returns
- * DMRT_ENONFINITE when the watchdog of dmrt_step has found a non-finite
- * state (then up to date). */
+/* Wait for all work enqueued on the handle's stream, after a watchdog check
+ * of the current state when steps were taken since the last one.  Returns
+ * DMRT_ENONFINITE when a check has found a non-finite state (then up to
+ * date). */
 int dmrt_sync(dmrt_cavity *h);
 
 /* Steps taken since the last (re)initialisation. */

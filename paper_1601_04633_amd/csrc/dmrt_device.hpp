@@ -203,7 +203,47 @@ struct StepArgs {
     // every step, step t + j at lp + (j - 1) lslot
     real* __restrict__ lp = nullptr;
     long lslot = 0;
+    // non-finite watchdog folded into the launch: the last wblocks
+    // workgroups of the grid check the wall columns of (fin, gin) and set
+    // *wflag when one holds a non-finite value (wall_check_blocks)
+    int* __restrict__ wflag = nullptr;
+    int wblocks = 0;
 };
+
+// Non-finite test of wall node t (0 <= t < 2n: row t / 2, column 0 for even
+// t, n - 1 for odd t) of the state (fs, gs): the sum of the magnitudes of
+// its 14 populations is not finite.  A non-finite value anywhere in the
+// cavity reaches one of the two wall columns within n steps (information
+// moves one node per step).
+template <typename real>
+__device__ __forceinline__ bool wall_node_bad(const real* __restrict__ fs, const real* __restrict__ gs, int n,
+                                              int pitch, int plane, int t)
+{
+    const int y = t >> 1, x = (t & 1) ? n - 1 : 0;
+    const int k = y * pitch + x;
+    real s = real(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s += fabs(fs[i * plane + k]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) s += fabs(gs[i * plane + k]);
+    return !isfinite(s);
+}
+
+// The workgroups past the stepping grid (the last A.wblocks of it, each
+// thread one wall node of the launch's input) run the watchdog and return
+// true; the others return false at once (a uniform test per workgroup).
+template <typename real>
+__device__ __forceinline__ bool wall_check_blocks(const StepArgs<real>& A)
+{
+    const int first = int(gridDim.x) - A.wblocks;
+    if (int(blockIdx.x) < first) return false;
+    const int nt = blockDim.x * blockDim.y;
+    const int t = (int(blockIdx.x) - first) * nt + threadIdx.y * blockDim.x + threadIdx.x;
+    int bad = t < 2 * A.n ? wall_node_bad(A.fin, A.gin, A.n, A.pitch, A.plane, t) : 0;
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0 && threadIdx.y == 0 && bad) *A.wflag = 1;
+    return true;
+}
 
 // Temperature sum of a node's post-collision g in FP64, in the order the
 // Nusselt kernels use, into the sample slot of step t + j when x is 0 or 1
@@ -414,7 +454,8 @@ __device__ __forceinline__ double node_update(const real* __restrict__ fi, const
 template <typename real, int BC>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs<real> A)
 {
-    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (wall_check_blocks(A)) return;
+    const int tile = tile_of_block(blockIdx.x, gridDim.x - A.wblocks, A.xcd_remap);
     if (tile >= A.tiles) return;
     const int ty = tile / A.tiles_x;
     const int tx = tile - ty * A.tiles_x;
@@ -1002,7 +1043,8 @@ template <typename real, int R, int K>
 __global__ void __launch_bounds__(kFootW * R) stepk_kernel(StepArgs<real> A)
 {
     __shared__ real lds[14 * R * kFootW];
-    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (wall_check_blocks(A)) return;
+    const int tile = tile_of_block(blockIdx.x, gridDim.x - A.wblocks, A.xcd_remap);
     if (tile >= A.tiles) return;                      // uniform per workgroup
     stepk_tile<real, R, K, false>(A, lds, tile);
 }
@@ -1317,7 +1359,8 @@ __device__ __forceinline__ void stepm_body(const StepArgs<real>& A, int chunk)
     constexpr int RS = B + 2, W = kFootW - 2 * (K - 1), RING = 14 * RS * kFootW;
     static_assert(K >= 2 && W > 0, "K out of range");
     __shared__ real lds[(K - 1) * RING];
-    const int tile = tile_of_block(blockIdx.x, gridDim.x, A.xcd_remap);
+    if (wall_check_blocks(A)) return;
+    const int tile = tile_of_block(blockIdx.x, gridDim.x - A.wblocks, A.xcd_remap);
     if (tile >= A.tiles) return;                      // uniform per workgroup
     const int tyt = tile / A.tiles_x;
     const int txt = tile - tyt * A.tiles_x;
@@ -1820,29 +1863,17 @@ __global__ void __launch_bounds__(256) batch_check_kernel(const CavityDev<real>*
     if (threadIdx.x == 0 && bad) atomicOr(&flags[blockIdx.y], 1);
 }
 
-// Watchdog of dmrt_step: the populations of the two isothermal-wall columns
-// (x = 0 and x = n - 1, all 14 planes).  A non-finite value anywhere in the
-// cavity reaches one of them within n steps (information moves one node per
-// step).  One thread per wall node (grid of ceil(2n / 256) workgroups), so
-// the check costs about one memory latency; sets *flag (pinned host memory)
-// when one is found.
+// The watchdog of wall_check_blocks as a launch of its own (for a state no
+// stepping launch reads next): one thread per wall node, a grid of
+// ceil(2n / 256) workgroups; sets *flag (pinned host memory) when a wall
+// node holds a non-finite value.
 template <typename real>
 __global__ void __launch_bounds__(256) wall_check_kernel(const real* __restrict__ fs,
                                                          const real* __restrict__ gs, int n, int pitch,
                                                          int plane, int* __restrict__ flag)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int bad = 0;
-    if (t < 2 * n) {
-        const int y = t >> 1, x = (t & 1) ? n - 1 : 0;
-        const int k = y * pitch + x;
-        real s = real(0);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) s += fabs(fs[i * plane + k]);
-#pragma unroll
-        for (int i = 0; i < 5; ++i) s += fabs(gs[i * plane + k]);
-        bad = !isfinite(s);
-    }
+    int bad = t < 2 * n ? wall_node_bad(fs, gs, n, pitch, plane, t) : 0;
     bad = __syncthreads_or(bad);
     if (threadIdx.x == 0 && bad) *flag = 1;
 }

@@ -165,6 +165,7 @@ int launch_step_t(dmrt_cavity* h, hipStream_t s, int from)
     A.c = make_coef<real>(h->p, h->d);
     int nblocks = A.tiles;
     if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
+    nblocks += add_wall_check(h, A, h->block_x * h->block_y);
     dim3 grid(nblocks), block(h->block_x, h->block_y);
     switch (h->p.bc_mode) {
     case DMRT_BC_CAVITY: hipLaunchKernelGGL((step_kernel<real, BC_CAVITY>), grid, block, 0, s, A); break;
@@ -324,12 +325,14 @@ int enqueue_steps(dmrt_cavity* h, hipStream_t s, int from, long base, long count
                                                fptr<float>(h, c ^ 1), gptr<float>(h, c ^ 1), slots, mask, m);
             pend += ns;
             i += m;
+            h->wcheck = false;                       // the first launch took the watchdog
             if (rc) return rc;
             c ^= 1;
             ++nflip;
         } else {
             rc = launch_step(h, s, c);
             i += 1;
+            h->wcheck = false;
             if (rc) return rc;
             c ^= 1;
             ++nflip;
@@ -621,10 +624,20 @@ int dmrt_step(dmrt_cavity* h, long nsteps)
     if (!h || nsteps < 0) return DMRT_EINVAL;
     DeviceGuard g(h->dev);
     if (!g.ok) return record_hip(hipErrorInvalidDevice, "hipSetDevice");
-    // a watchdog check of an earlier call (finished by now or not) found a
+    // a watchdog pass of an earlier call (finished by now or not) found a
     // non-finite state: report it and enqueue nothing
     if (*h->nonfinite) return DMRT_ENONFINITE;
+    if (nsteps == 0) return DMRT_OK;
     const int unit = graph_unit(h);
+    // the watchdog runs on the state this call starts from: in the workgroups
+    // its first launch appends, or on its own before a graph replay
+    const bool graph_first = unit > 0 && (h->step % unit) == 0 && nsteps >= unit;
+    if (graph_first) {
+        const int rc = launch_wall_check(h);
+        if (rc) return rc;
+    }
+    h->wcheck = !graph_first;
+    h->unchecked = true;
     long left = nsteps;
     while (left > 0) {
         const bool aligned = unit > 0 && (h->step % unit) == 0;
@@ -654,19 +667,25 @@ int dmrt_step(dmrt_cavity* h, long nsteps)
             }
             int flips = 0;
             int rc = enqueue_steps(h, h->stream, h->cur, h->step, chunk, &flips);
+            h->wcheck = false;
             if (rc) return rc;
             h->step += chunk;
             if (flips & 1) h->cur ^= 1;
             left -= chunk;
         }
     }
-    return nsteps > 0 ? launch_wall_check(h) : DMRT_OK;
+    return DMRT_OK;
 }
 
 int dmrt_sync(dmrt_cavity* h)
 {
     if (!h) return DMRT_EINVAL;
     DeviceGuard g(h->dev);
+    if (h->unchecked) {               // the state the last call left
+        const int rc = launch_wall_check(h);
+        if (rc) return rc;
+        h->unchecked = false;
+    }
     HIPCHK(hipStreamSynchronize(h->stream));
     return *h->nonfinite ? DMRT_ENONFINITE : DMRT_OK;
 }

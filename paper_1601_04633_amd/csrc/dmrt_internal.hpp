@@ -97,9 +97,14 @@ struct dmrt_cavity {
     // initial temperature of the last dmrt_set_theta (gradient problem)
     double* theta0 = nullptr;         // n^2 doubles
     bool theta0_valid = false;
-    // set by the watchdog kernel after a dmrt_step call found a non-finite
-    // value in a wall column (pinned host memory, written by the device)
+    // set by the watchdog after it found a non-finite value in a wall
+    // column (pinned host memory, written by the device)
     volatile int* nonfinite = nullptr;
+    // the next stepping launch runs the watchdog on its input (extra
+    // workgroups; set for the first launch of a dmrt_step call)
+    bool wcheck = false;
+    // steps enqueued since the last watchdog pass (dmrt_sync runs one)
+    bool unchecked = false;
     dmrt::AdjointState* adj = nullptr;
     long adj_gen = 0;                 // successful dmrt_adjoint_forward calls
 };
@@ -176,6 +181,18 @@ int march_chunk_auto(int n, int K, int B, int dev)
     return std::max(1, (n + chunks - 1) / chunks);
 }
 
+// Workgroups to append to a stepping launch of `threads` threads per
+// workgroup so that it also runs the watchdog on its input (h->wcheck set;
+// the launch's kernel calls wall_check_blocks), else 0.
+template <typename real>
+int add_wall_check(const dmrt_cavity* h, StepArgs<real>& A, int threads)
+{
+    if (!h->wcheck) return 0;
+    A.wflag = const_cast<int*>(h->nonfinite);
+    A.wblocks = (2 * h->n + threads - 1) / threads;
+    return A.wblocks;
+}
+
 // Launches K = h->temporal steps of the cavity with the row-marching kernel
 // (h->march wave rows per step group, h->march_chunk rows per workgroup),
 // or k < K steps in the shape of h->march_rem_B[k] and h->march_rem_chunk[k].
@@ -198,6 +215,7 @@ int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
     A.c = make_coef<real>(h->p, h->d);
     int nblocks = A.tiles;
     if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
+    nblocks += add_wall_check(h, A, kFootW * K * B);
     const dim3 grid(nblocks), block(kFootW, K * B);
 #define DMRT_KB(KK, BB)                                                                  \
     if constexpr (march_lds_bytes(KK, BB, sizeof(real)) <= kLdsBytes)                     \
@@ -238,6 +256,7 @@ int launch_stepk(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
     A.c = make_coef<real>(h->p, h->d);
     int nblocks = A.tiles;
     if (h->xcd_remap) nblocks = (nblocks + 7) / 8 * 8;
+    if (!acc) nblocks += add_wall_check(h, A, kFootW * R);   // stepk_kernel only
     const dim3 grid(nblocks), block(kFootW, R);
 #define DMRT_KR(KK, RR)                                                                   \
     if (K == KK && R == RR) {                                                              \

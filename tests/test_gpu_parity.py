@@ -299,17 +299,30 @@ def test_residual_and_watchdog():
     assert bad
 
 
+WATCHDOG_FORMS = {"single": (1, 10), "tile": (4, 12), "march6": ("march", 6, 2, 0)}
+
+
+def _set_form(c, form):
+    t = WATCHDOG_FORMS[form]
+    if t[0] == "march":
+        c.set_temporal_march(*t[1:])
+    else:
+        c.set_temporal(*t)
+
+
+@pytest.mark.parametrize("form", list(WATCHDOG_FORMS))
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_step_watchdog_reports_nonfinite_state(precision):
-    """dmrt_step's watchdog (the two isothermal-wall columns, checked after
-    every call) reports a NaN planted in the interior once it has spread to
-    a wall: dmrt_sync returns DMRT_ENONFINITE, later dmrt_step calls return
-    it without enqueuing, and re-initialising clears it; a healthy run never
-    reports it."""
+def test_step_watchdog_reports_nonfinite_state(precision, form):
+    """dmrt_step's watchdog (the two isothermal-wall columns of the state a
+    call starts from, checked by its first launch; dmrt_sync checks the
+    current state) reports a NaN planted in the interior once it has spread
+    to a wall: dmrt_sync returns DMRT_ENONFINITE, later dmrt_step calls
+    return it without enqueuing, and re-initialising clears it; a healthy
+    run never reports it."""
     from paper_1601_04633_amd.dmrt import Cavity, DmrtError, DMRT_ENONFINITE
     n = 40
     c = Cavity(n=n, Ra=1e4, Pr=0.01, precision=precision)
-    c.set_temporal(4, 12)
+    _set_form(c, form)
     c.set_theta(inputs.theta_noise(n, 16))
     c.step(300)
     c.sync()
@@ -331,6 +344,35 @@ def test_step_watchdog_reports_nonfinite_state(precision):
     c.set_theta(inputs.theta_noise(n, 16))
     c.step(100)
     c.sync()
+    c.close()
+
+
+@pytest.mark.parametrize("form", list(WATCHDOG_FORMS))
+def test_step_watchdog_in_first_launch(form):
+    """Without dmrt_sync: the check that the first launch of a dmrt_step
+    call runs on the state it starts from sets the flag, and the next call
+    returns DMRT_ENONFINITE (graphs off, so every call starts with a
+    stepping launch).  A NaN placed on a wall column is found by the first
+    call after it."""
+    import torch
+    from paper_1601_04633_amd.dmrt import Cavity, DmrtError, DMRT_ENONFINITE
+    n = 40
+    c = Cavity(n=n, Ra=1e4, Pr=0.01, precision="fp32")
+    _set_form(c, form)
+    c.set_launch(256, 1, 1, 0)
+    c.set_theta(inputs.theta_noise(n, 16))
+    c.step(30)
+    c.sync()
+    blob = bytearray(c.save_state())
+    # f plane 3 at node (x, y) = (n - 1, 25): on the cold wall
+    off = 8 * 8 + n * 8 + 4 * (3 * n * n + 25 * n + n - 1)
+    blob[off:off + 4] = np.array([np.inf], dtype=np.float32).tobytes()
+    c.load_state(bytes(blob))
+    c.step(7)                          # its first launch finds the wall value
+    torch.cuda.synchronize()           # the flag is written; no dmrt_sync
+    with pytest.raises(DmrtError) as e:
+        c.step(1)
+    assert e.value.code == DMRT_ENONFINITE
     c.close()
 
 
