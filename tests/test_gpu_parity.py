@@ -347,16 +347,40 @@ def test_step_watchdog_reports_nonfinite_state(precision, form):
     c.close()
 
 
-@pytest.mark.parametrize("form", list(WATCHDOG_FORMS))
-def test_step_watchdog_in_first_launch(form):
+def test_step_counts_not_multiple_of_k_full_size():
+    """The benchmark's cavity (1024^2 FP32, six steps per launch): counts
+    20, 13 and 7 (launches of 6+6+4+4, 6+4+3 and 4+3 steps) give bitwise the
+    state of single steps."""
+    from paper_1601_04633_amd.dmrt import Cavity
+    n = 1024
+    th0 = inputs.theta_noise(n, 1601, amp=1e-2)
+    counts = [20, 13, 7]
+    print(f"[parity] 1024^2 step counts {counts} in six-step marching vs single steps", flush=True)
+    out = []
+    for march in (False, True):
+        c = Cavity(n=n, Ra=1e5, Pr=0.001, precision="fp32")
+        if march:
+            c.set_temporal_march(6, 2, 0)
+        c.set_launch(256, 1, 1, 0)
+        c.set_theta(th0)
+        for k in counts:
+            c.step(k)
+        out.append(c.raw_state())
+        c.close()
+    (fa, ga), (fb, gb) = out
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+@pytest.mark.parametrize("form,n", [(f, 40) for f in WATCHDOG_FORMS] + [("march6", 1024)])
+def test_step_watchdog_in_first_launch(form, n):
     """Without dmrt_sync: the check that the first launch of a dmrt_step
     call runs on the state it starts from sets the flag, and the next call
     returns DMRT_ENONFINITE (graphs off, so every call starts with a
     stepping launch).  A NaN placed on a wall column is found by the first
-    call after it."""
+    call after it (at 1024^2 in the last of the three workgroups that the
+    six-step launch appends)."""
     import torch
     from paper_1601_04633_amd.dmrt import Cavity, DmrtError, DMRT_ENONFINITE
-    n = 40
     c = Cavity(n=n, Ra=1e4, Pr=0.01, precision="fp32")
     _set_form(c, form)
     c.set_launch(256, 1, 1, 0)
@@ -364,8 +388,10 @@ def test_step_watchdog_in_first_launch(form):
     c.step(30)
     c.sync()
     blob = bytearray(c.save_state())
-    # f plane 3 at node (x, y) = (n - 1, 25): on the cold wall
-    off = 8 * 8 + n * 8 + 4 * (3 * n * n + 25 * n + n - 1)
+    # f plane 3 at node (x, y) = (n - 1, yw): on the cold wall, in the
+    # last rows (wall node 2 yw + 1 of the check's 2n)
+    yw = n - 15
+    off = 8 * 8 + n * 8 + 4 * (3 * n * n + yw * n + n - 1)
     blob[off:off + 4] = np.array([np.inf], dtype=np.float32).tobytes()
     c.load_state(bytes(blob))
     c.step(7)                          # its first launch finds the wall value
