@@ -1236,7 +1236,7 @@ __device__ __forceinline__ void march_loads(const StepArgs<real>& A, const unsig
 // gather from the previous group's ring.  Whether the wave computes is
 // decided per wave (its row); all its lanes compute, and only the global
 // stores and the Nusselt sums are limited to the group's columns.
-template <typename real, int K, int B, bool FIRST, bool SAMP>
+template <typename real, int K, int B, bool FIRST, bool SAMP, bool PAIRED = false>
 __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchWave<real>& w, MarchPos& p,
                                            real (&cf)[9], real (&cg)[5], real (&nf)[9], real (&ng)[5])
 {
@@ -1280,13 +1280,20 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
         }
     }
     __syncthreads();
-    // next row: B further, each ring slot B further round the ring
-    constexpr int STEP = B * kFootW, WRAP = RS * kFootW;
-    p.v = v + B;
-    p.y = y + w.ydir * B;
-    p.olo = p.olo + STEP >= WRAP ? p.olo + STEP - WRAP : p.olo + STEP;
-    p.o0 = p.o0 + STEP >= WRAP ? p.o0 + STEP - WRAP : p.o0 + STEP;
-    p.ohi = p.ohi + STEP >= WRAP ? p.ohi + STEP - WRAP : p.ohi + STEP;
+    if constexpr (PAIRED) {
+        // the caller alternates two positions whose ring slots repeat
+        // every two iterations (2B a multiple of B + 2): only the row moves
+        p.v = v + 2 * B;
+        p.y = y + 2 * w.ydir * B;
+    } else {
+        // next row: B further, each ring slot B further round the ring
+        constexpr int STEP = B * kFootW, WRAP = RS * kFootW;
+        p.v = v + B;
+        p.y = y + w.ydir * B;
+        p.olo = p.olo + STEP >= WRAP ? p.olo + STEP - WRAP : p.olo + STEP;
+        p.o0 = p.o0 + STEP >= WRAP ? p.o0 + STEP - WRAP : p.o0 + STEP;
+        p.ohi = p.ohi + STEP >= WRAP ? p.ohi + STEP - WRAP : p.ohi + STEP;
+    }
 }
 
 // One workgroup's sweep: the column band whose footprint starts at column
@@ -1347,6 +1354,20 @@ __device__ __forceinline__ void stepm_sweep(const StepArgs<real>& A, real* lds, 
         for (int i = 0; i < T; i += 2) {
             march_iter<real, K, B, true, SAMP>(A, w, p, af, ag, bf, bg);
             if (i + 1 < T) march_iter<real, K, B, true, SAMP>(A, w, p, bf, bg, af, ag);
+        }
+    } else if constexpr ((2 * B) % RS == 0) {
+        // two rows per group: the ring slots of a wave repeat every two
+        // iterations, so two positions with fixed slots alternate and the
+        // ring addresses stay the same from one trip to the next
+        MarchPos q = p;
+        q.v = p.v + B;
+        q.y = p.y + w.ydir * B;
+        q.olo = (p.olo + B * kFootW) % (RS * kFootW);
+        q.o0 = (p.o0 + B * kFootW) % (RS * kFootW);
+        q.ohi = (p.ohi + B * kFootW) % (RS * kFootW);
+        for (int i = 0; i < T; i += 2) {
+            march_iter<real, K, B, false, SAMP, true>(A, w, p, af, ag, bf, bg);
+            if (i + 1 < T) march_iter<real, K, B, false, SAMP, true>(A, w, q, af, ag, bf, bg);
         }
     } else {
         for (int i = 0; i < T; ++i) march_iter<real, K, B, false, SAMP>(A, w, p, af, ag, bf, bg);
