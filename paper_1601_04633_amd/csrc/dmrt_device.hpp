@@ -1098,7 +1098,7 @@ __global__ void __launch_bounds__(kFootW * R) stepk_rec_kernel(StepArgs<real> A)
 // output columns may run it too.
 template <typename real, int B>
 __device__ __forceinline__ void gather_ring(const real* ring, const real* thw, bool wall, int n, int x, int y,
-                                            int om, int o0, int op, const Coef<real>& c, real (&f)[9],
+                                            int om, int o0, int op, int o8, const Coef<real>& c, real (&f)[9],
                                             real (&g)[5])
 {
     constexpr int PL = (B + 2) * kFootW;
@@ -1113,7 +1113,7 @@ __device__ __forceinline__ void gather_ring(const real* ring, const real* thw, b
     f[5] = bm[5 * PL - 1];
     f[6] = bm[6 * PL + 1];
     f[7] = bp[7 * PL + 1];
-    f[8] = bp[8 * PL - 1];
+    f[8] = bp[o8];                // o8 = 8 PL - 1, opaque to the compiler (see MarchWave)
     g[0] = b0[9 * PL];
     g[1] = b0[10 * PL - 1];
     g[2] = bm[11 * PL];
@@ -1149,6 +1149,11 @@ struct MarchWave {
     const real* rin;     // previous group's ring at this lane
     real* rout;          // own ring at this lane
     unsigned off[9];
+    // ring offset of link 8 in its source row, 8 (B + 2) 64 - 1, held in a
+    // register the compiler cannot see through: with a constant it would
+    // pair that read with link 7's (one 64-bit LDS read into adjacent
+    // registers) and then copy both values out of the pair every row
+    int o8;
 };
 
 // Uniform position of a wave in its sweep: marching row v, the cavity row
@@ -1250,7 +1255,7 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
         if (row && w.wallx) gather_cavity_walls<real>(thw_row<real>(A.thw, y), n, w.x, A.c, cg);
     } else if (row) {
         gather_ring<real, B>(w.rin, A.thw, w.wallx || y == 0 || y == n - 1, n, w.x, y, p.olo, p.o0, p.ohi,
-                             A.c, cf, cg);
+                             w.o8, A.c, cf, cg);
     }
     if (row) {
         real th, ux, uy;
@@ -1327,6 +1332,8 @@ __device__ __forceinline__ void stepm_sweep(const StepArgs<real>& A, real* lds, 
     w.y0 = y0;
     w.y1 = y1;
     w.xact = w.x >= 0 && w.x < n && lx >= w.j - 1 && lx <= kFootW - w.j;
+    w.o8 = 8 * RS * kFootW - 1;
+    asm("" : "+v"(w.o8));
     w.rin = lds + (w.j >= 2 ? (w.j - 2) * RING : 0) + lx;
     w.rout = lds + (w.j < K ? (w.j - 1) * RING : 0) + lx;
     const int xn = min(max(w.x, 0), n - 1);           // lanes outside the cavity gather a clamped column
