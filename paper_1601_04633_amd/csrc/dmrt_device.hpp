@@ -1154,6 +1154,10 @@ struct MarchWave {
     // pair that read with link 7's (one 64-bit LDS read into adjacent
     // registers) and then copy both values out of the pair every row
     int o8;
+    // the force's constant term in a vector register for the whole sweep
+    // (its multiply-add also takes gbh from a scalar register, and one
+    // instruction reads at most one)
+    real gy0h;
 };
 
 // Uniform position of a wave in its sweep: marching row v, the cavity row
@@ -1259,7 +1263,9 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
     }
     if (row) {
         real th, ux, uy;
-        collide<real>(cf, cg, A.c, th, ux, uy);
+        Coef<real> c = A.c;
+        c.gy0h = w.gy0h;
+        collide<real>(cf, cg, c, th, ux, uy);
         // a Nusselt sample due at this group's step: rows of this chunk only
         if (SAMP && w.samp && y >= w.y0 && y < w.y1 && w.xact) samp_put<real>(A, w.j, w.x, y, cg);
     }
@@ -1334,6 +1340,8 @@ __device__ __forceinline__ void stepm_sweep(const StepArgs<real>& A, real* lds, 
     w.xact = w.x >= 0 && w.x < n && lx >= w.j - 1 && lx <= kFootW - w.j;
     w.o8 = 8 * RS * kFootW - 1;
     asm("" : "+v"(w.o8));
+    w.gy0h = A.c.gy0h;
+    asm("" : "+v"(w.gy0h));
     w.rin = lds + (w.j >= 2 ? (w.j - 2) * RING : 0) + lx;
     w.rout = lds + (w.j < K ? (w.j - 1) * RING : 0) + lx;
     const int xn = min(max(w.x, 0), n - 1);           // lanes outside the cavity gather a clamped column
