@@ -1120,17 +1120,29 @@ __device__ __forceinline__ void gather_ring(const real* ring, const real* thw, b
     g[3] = b0[12 * PL + 1];
     g[4] = bp[13 * PL];
     if (!wall) return;
+    // A link that crosses a wall takes the node's own value of the opposite
+    // link (halfway bounce-back; Eq. 45 adds the wall temperature on the
+    // left, Eq. 44's adiabatic walls bounce g back).  Every lane of a wall
+    // wave reads those own-node values together and then selects: one read
+    // per lane-dependent branch would make the wave wait for each in turn.
     const real thw_y = thw_row<real>(thw, y);
     const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
-    if (!(hxm && hxp && hym && hyp)) {
-        if (!hxm) { f[1] = b0[3 * PL]; g[1] = fmr(c.cabb, thw_y, -b0[12 * PL]); }   // Eq. 45
-        if (!hxp) { f[3] = b0[1 * PL]; g[3] = c.cold - b0[10 * PL]; }
-        if (!hym) { f[2] = b0[4 * PL]; g[2] = b0[13 * PL]; }                           // Eq. 44
-        if (!hyp) { f[4] = b0[2 * PL]; g[4] = b0[11 * PL]; }
-        if (!(hxm && hym)) f[5] = b0[7 * PL];
-        if (!(hxp && hym)) f[6] = b0[8 * PL];
-        if (!(hxp && hyp)) f[7] = b0[5 * PL];
-        if (!(hxm && hyp)) f[8] = b0[6 * PL];
+    const real r1 = b0[3 * PL], r3 = b0[1 * PL], s1 = b0[12 * PL], s3 = b0[10 * PL];
+    const real r5 = b0[7 * PL], r6 = b0[8 * PL], r7 = b0[5 * PL], r8 = b0[6 * PL];
+    f[1] = hxm ? f[1] : r1;
+    g[1] = hxm ? g[1] : fmr(c.cabb, thw_y, -s1);                  // Eq. 45
+    f[3] = hxp ? f[3] : r3;
+    g[3] = hxp ? g[3] : c.cold - s3;
+    f[5] = hxm && hym ? f[5] : r5;
+    f[6] = hxp && hym ? f[6] : r6;
+    f[7] = hxp && hyp ? f[7] : r7;
+    f[8] = hxm && hyp ? f[8] : r8;
+    if (!(hym && hyp)) {                                          // bottom or top row (y is uniform)
+        const real r2 = b0[4 * PL], r4 = b0[2 * PL], s2 = b0[13 * PL], s4 = b0[11 * PL];
+        f[2] = hym ? f[2] : r2;                                   // Eq. 44
+        g[2] = hym ? g[2] : s2;
+        f[4] = hyp ? f[4] : r4;
+        g[4] = hyp ? g[4] : s4;
     }
 }
 
