@@ -878,14 +878,25 @@ __device__ __forceinline__ void gather_lds(const real* lds, const real* __restri
     g[4] = b[13 * PL + W];
     const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
     if (!(hxm && hxp && hym && hyp)) {
-        if (!hxm) { f[1] = b[3 * PL]; g[1] = fmr(c.cabb, thw[y], -b[12 * PL]); }   // Eq. 45
-        if (!hxp) { f[3] = b[1 * PL]; g[3] = c.cold - b[10 * PL]; }
-        if (!hym) { f[2] = b[4 * PL]; g[2] = b[13 * PL]; }                          // Eq. 44
-        if (!hyp) { f[4] = b[2 * PL]; g[4] = b[11 * PL]; }
-        if (!(hxm && hym)) f[5] = b[7 * PL];
-        if (!(hxp && hym)) f[6] = b[8 * PL];
-        if (!(hxp && hyp)) f[7] = b[5 * PL];
-        if (!(hxm && hyp)) f[8] = b[6 * PL];
+        // a lane on a wall (0 <= x, y < n for every caller): all own-node
+        // values its wall links may take, read together, then selected; a
+        // read per branch would make the wave wait for each in turn
+        const real r1 = b[3 * PL], s1 = b[12 * PL], r3 = b[1 * PL], s3 = b[10 * PL];
+        const real r2 = b[4 * PL], s2 = b[13 * PL], r4 = b[2 * PL], s4 = b[11 * PL];
+        const real r5 = b[7 * PL], r6 = b[8 * PL], r7 = b[5 * PL], r8 = b[6 * PL];
+        const real tw = thw[y];
+        f[1] = hxm ? f[1] : r1;
+        g[1] = hxm ? g[1] : fmr(c.cabb, tw, -s1);                  // Eq. 45
+        f[3] = hxp ? f[3] : r3;
+        g[3] = hxp ? g[3] : c.cold - s3;
+        f[2] = hym ? f[2] : r2;
+        g[2] = hym ? g[2] : s2;                                    // Eq. 44
+        f[4] = hyp ? f[4] : r4;
+        g[4] = hyp ? g[4] : s4;
+        f[5] = hxm && hym ? f[5] : r5;
+        f[6] = hxp && hym ? f[6] : r6;
+        f[7] = hxp && hyp ? f[7] : r7;
+        f[8] = hxm && hyp ? f[8] : r8;
     }
 }
 
@@ -1457,14 +1468,23 @@ __device__ __forceinline__ void adj_pull_lds(const real* lds, int n, int x, int 
     lg[4] = b[13 * PL - W] + sd;
     const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
     if (!(hxm && hxp && hym && hyp)) {
-        if (!hxp) { lf[1] = b[3 * PL]; lg[1] = sd - b[12 * PL]; }      // Eq. 45, right wall
-        if (!hxm) { lf[3] = b[1 * PL]; lg[3] = sd - b[10 * PL]; }      // Eq. 45, left wall
-        if (!hyp) { lf[2] = b[4 * PL]; lg[2] = b[13 * PL] + sd; }      // Eq. 44
-        if (!hym) { lf[4] = b[2 * PL]; lg[4] = b[11 * PL] + sd; }
-        if (!(hxp && hyp)) lf[5] = b[7 * PL];
-        if (!(hxm && hyp)) lf[6] = b[8 * PL];
-        if (!(hxm && hym)) lf[7] = b[5 * PL];
-        if (!(hxp && hym)) lf[8] = b[6 * PL];
+        // a lane on a wall: the own-node values read together, then selected
+        // (a read per branch would make the wave wait for each in turn)
+        const real r1 = b[3 * PL], s1 = b[12 * PL], r3 = b[1 * PL], s3 = b[10 * PL];
+        const real r2 = b[4 * PL], s2 = b[13 * PL], r4 = b[2 * PL], s4 = b[11 * PL];
+        const real r5 = b[7 * PL], r6 = b[8 * PL], r7 = b[5 * PL], r8 = b[6 * PL];
+        lf[1] = hxp ? lf[1] : r1;
+        lg[1] = hxp ? lg[1] : sd - s1;                                 // Eq. 45, right wall
+        lf[3] = hxm ? lf[3] : r3;
+        lg[3] = hxm ? lg[3] : sd - s3;                                 // Eq. 45, left wall
+        lf[2] = hyp ? lf[2] : r2;
+        lg[2] = hyp ? lg[2] : s2 + sd;                                 // Eq. 44
+        lf[4] = hym ? lf[4] : r4;
+        lg[4] = hym ? lg[4] : s4 + sd;
+        lf[5] = hxp && hyp ? lf[5] : r5;
+        lf[6] = hxm && hyp ? lf[6] : r6;
+        lf[7] = hxm && hym ? lf[7] : r7;
+        lf[8] = hxp && hym ? lf[8] : r8;
     }
 }
 
