@@ -1108,7 +1108,7 @@ __global__ void __launch_bounds__(kFootW * R) stepk_rec_kernel(StepArgs<real> A)
 // read stays inside the ring for any lane, so lanes outside the band's
 // output columns may run it too.
 template <typename real, int B>
-__device__ __forceinline__ void gather_ring(const real* ring, const real* thw, bool wall, int n, int x, int y,
+__device__ __forceinline__ void gather_ring(const real* ring, const real* thw, int wallx, int n, int x, int y,
                                             int om, int o0, int op, int o8, const Coef<real>& c, real (&f)[9],
                                             real (&g)[5])
 {
@@ -1130,30 +1130,43 @@ __device__ __forceinline__ void gather_ring(const real* ring, const real* thw, b
     g[2] = bm[11 * PL];
     g[3] = b0[12 * PL + 1];
     g[4] = bp[13 * PL];
-    if (!wall) return;
-    // A link that crosses a wall takes the node's own value of the opposite
+    // Links that cross a wall take the node's own value of the opposite
     // link (halfway bounce-back; Eq. 45 adds the wall temperature on the
-    // left, Eq. 44's adiabatic walls bounce g back).  Every lane of a wall
-    // wave reads those own-node values together and then selects: one read
-    // per lane-dependent branch would make the wave wait for each in turn.
-    const real thw_y = thw_row<real>(thw, y);
-    const bool hxm = x > 0, hxp = x < n - 1, hym = y > 0, hyp = y < n - 1;
-    const real r1 = b0[3 * PL], r3 = b0[1 * PL], s1 = b0[12 * PL], s3 = b0[10 * PL];
-    const real r5 = b0[7 * PL], r6 = b0[8 * PL], r7 = b0[5 * PL], r8 = b0[6 * PL];
-    f[1] = hxm ? f[1] : r1;
-    g[1] = hxm ? g[1] : fmr(c.cabb, thw_y, -s1);                  // Eq. 45
-    f[3] = hxp ? f[3] : r3;
-    g[3] = hxp ? g[3] : c.cold - s3;
-    f[5] = hxm && hym ? f[5] : r5;
-    f[6] = hxp && hym ? f[6] : r6;
-    f[7] = hxp && hyp ? f[7] : r7;
-    f[8] = hxm && hyp ? f[8] : r8;
-    if (!(hym && hyp)) {                                          // bottom or top row (y is uniform)
-        const real r2 = b0[4 * PL], r4 = b0[2 * PL], s2 = b0[13 * PL], s4 = b0[11 * PL];
-        f[2] = hym ? f[2] : r2;                                   // Eq. 44
-        g[2] = hym ? g[2] : s2;
-        f[4] = hyp ? f[4] : r4;
-        g[4] = hyp ? g[4] : s4;
+    // left, Eq. 44's adiabatic walls bounce g back).  wallx (bit 0: the
+    // band holds the left wall, bit 1: the right one) and the row are
+    // uniform per wave, so each wall is a uniform branch; within a side-wall
+    // band every lane reads the own-node values together and then selects
+    // (one read per lane-dependent branch would wait for each in turn).
+    const bool bot = y == 0, top = y == n - 1;
+    if (!wallx && !bot && !top) return;
+    if (wallx & 1) {                                              // x = 0
+        const bool in = x > 0;
+        const real r1 = b0[3 * PL], s1 = b0[12 * PL], r5 = b0[7 * PL], r8 = b0[6 * PL];
+        const real tw = thw_row<real>(thw, y);
+        f[1] = in ? f[1] : r1;
+        g[1] = in ? g[1] : fmr(c.cabb, tw, -s1);                  // Eq. 45
+        f[5] = in ? f[5] : r5;
+        f[8] = in ? f[8] : r8;
+    }
+    if (wallx & 2) {                                              // x = n - 1
+        const bool in = x < n - 1;
+        const real r3 = b0[1 * PL], s3 = b0[10 * PL], r6 = b0[8 * PL], r7 = b0[5 * PL];
+        f[3] = in ? f[3] : r3;
+        g[3] = in ? g[3] : c.cold - s3;                           // Eq. 45
+        f[6] = in ? f[6] : r6;
+        f[7] = in ? f[7] : r7;
+    }
+    if (bot) {                                                    // Eq. 44, y = 0
+        f[2] = b0[4 * PL];
+        g[2] = b0[13 * PL];
+        f[5] = b0[7 * PL];
+        f[6] = b0[8 * PL];
+    }
+    if (top) {                                                    // Eq. 44, y = n - 1
+        f[4] = b0[2 * PL];
+        g[4] = b0[11 * PL];
+        f[7] = b0[5 * PL];
+        f[8] = b0[6 * PL];
     }
 }
 
@@ -1166,7 +1179,7 @@ struct MarchWave {
     int j, x, y0, y1;
     int ydir;            // marching row v stands for cavity row ybase + ydir v
     int vlo, vhi;        // marching rows this group computes: its rows of the chunk, inside the cavity
-    int wallx;           // a lane of the band sits on the left or right wall
+    int wallx;           // the band holds the left wall (bit 0) or the right one (bit 1)
     int samp;            // a Nusselt sample is due at this group's step
     bool xact;           // the lane's column is one of this group's, inside the cavity
     const real* rin;     // previous group's ring at this lane
@@ -1281,8 +1294,7 @@ __device__ __forceinline__ void march_iter(const StepArgs<real>& A, const MarchW
         march_loads<real>(A, w.off, min(max(y + w.ydir * B, 0), n - 1), nf, ng);
         if (row && w.wallx) gather_cavity_walls<real>(thw_row<real>(A.thw, y), n, w.x, A.c, cg);
     } else if (row) {
-        gather_ring<real, B>(w.rin, A.thw, w.wallx || y == 0 || y == n - 1, n, w.x, y, p.olo, p.o0, p.ohi,
-                             w.o8, A.c, cf, cg);
+        gather_ring<real, B>(w.rin, A.thw, w.wallx, n, w.x, y, p.olo, p.o0, p.ohi, w.o8, A.c, cf, cg);
     }
     if (row) {
         real th, ux, uy;
@@ -1356,7 +1368,7 @@ __device__ __forceinline__ void stepm_sweep(const StepArgs<real>& A, real* lds, 
     // cavity rows lie in [0, n)
     w.vlo = max(y0 - (K - w.j), down ? ybase - n + 1 : 0);
     w.vhi = min(y1 + (K - w.j), down ? ybase + 1 : n);
-    w.wallx = (x_band <= 0 && x_band + kFootW > 0) || (x_band <= n - 1 && x_band + kFootW > n - 1);
+    w.wallx = (x_band <= 0 && x_band + kFootW > 0 ? 1 : 0) | (x_band <= n - 1 && x_band + kFootW > n - 1 ? 2 : 0);
     w.samp = (A.samp_mask >> w.j) & 1;
     w.y0 = y0;
     w.y1 = y1;
