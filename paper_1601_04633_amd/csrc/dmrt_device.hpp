@@ -1424,8 +1424,12 @@ __device__ __forceinline__ void stepm_sweep(const StepArgs<real>& A, real* lds, 
     }
 }
 
+// Tiles of a marching launch: first the bands without a side wall (1 ...
+// tiles_x - 2), chunk rows each, chunk row by chunk row; then the two bands
+// that hold the side walls, chunk_w rows each, the left and right band of a
+// chunk row in turn (a single band holds both walls).
 template <typename real, int K, int B, bool SAMP>
-__device__ __forceinline__ void stepm_body(const StepArgs<real>& A, int chunk)
+__device__ __forceinline__ void stepm_body(const StepArgs<real>& A, int chunk, int chunk_w)
 {
     constexpr int RS = B + 2, W = kFootW - 2 * (K - 1), RING = 14 * RS * kFootW;
     static_assert(K >= 2 && W > 0, "K out of range");
@@ -1433,26 +1437,37 @@ __device__ __forceinline__ void stepm_body(const StepArgs<real>& A, int chunk)
     if (wall_check_blocks(A)) return;
     const int tile = tile_of_block(blockIdx.x, gridDim.x - A.wblocks, A.xcd_remap);
     if (tile >= A.tiles) return;                      // uniform per workgroup
-    const int tyt = tile / A.tiles_x;
-    const int txt = tile - tyt * A.tiles_x;
-    const int y0 = tyt * chunk;
+    const int nb = A.tiles_x;
+    const int ni = nb > 2 ? (nb - 2) * ((A.n + chunk - 1) / chunk) : 0;
+    int txt, tyt, ch;
+    if (tile < ni) {
+        tyt = tile / (nb - 2);
+        txt = 1 + (tile - tyt * (nb - 2));
+        ch = chunk;
+    } else {
+        const int t = tile - ni;
+        tyt = nb == 1 ? t : t >> 1;
+        txt = nb == 1 ? 0 : ((t & 1) ? nb - 1 : 0);
+        ch = chunk_w;
+    }
+    const int y0 = tyt * ch;
     // odd chunks march down (row y0 + y1 - 1 - v for marching row v), so
     // that two neighbouring chunks read the rows they share at the same
     // time, at the end of both sweeps or at the start of both
-    stepm_sweep<real, K, B, SAMP>(A, lds, txt * W - (K - 1), y0, min(y0 + chunk, A.n), (tyt & 1) != 0);
+    stepm_sweep<real, K, B, SAMP>(A, lds, txt * W - (K - 1), y0, min(y0 + ch, A.n), (tyt & 1) != 0);
 }
 
 template <typename real, int K, int B>
-__global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A, int chunk)
+__global__ void __launch_bounds__(kFootW * K * B) stepm_kernel(StepArgs<real> A, int chunk, int chunk_w)
 {
-    stepm_body<real, K, B, false>(A, chunk);
+    stepm_body<real, K, B, false>(A, chunk, chunk_w);
 }
 
 // The same with Nusselt samples taken in the launch (samp_mask non-zero).
 template <typename real, int K, int B>
-__global__ void __launch_bounds__(kFootW * K * B) stepm_samp_kernel(StepArgs<real> A, int chunk)
+__global__ void __launch_bounds__(kFootW * K * B) stepm_samp_kernel(StepArgs<real> A, int chunk, int chunk_w)
 {
-    stepm_body<real, K, B, true>(A, chunk);
+    stepm_body<real, K, B, true>(A, chunk, chunk_w);
 }
 
 // lambda at footprint node (lx, ly) from mu of the previous phase in LDS:

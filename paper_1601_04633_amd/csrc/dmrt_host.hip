@@ -926,11 +926,11 @@ int dmrt_set_temporal_march(dmrt_cavity* h, int steps_per_launch, int group_rows
     if (!valid_march(steps_per_launch, group_rows, int(h->esz)) || chunk_rows < 0) return DMRT_EINVAL;
     if (h->p.bc_mode != DMRT_BC_CAVITY) return DMRT_EINVAL;
     DeviceGuard g(h->dev);
-    int chunk = chunk_rows;
+    int chunk = chunk_rows, chunk_w = chunk_rows;   // a given chunk serves every band
     if (chunk == 0)
         chunk = h->esz == sizeof(double)
-                    ? march_chunk_auto<double>(h->n, steps_per_launch, group_rows, h->dev)
-                    : march_chunk_auto<float>(h->n, steps_per_launch, group_rows, h->dev);
+                    ? march_chunk_auto<double>(h->n, steps_per_launch, group_rows, h->dev, &chunk_w)
+                    : march_chunk_auto<float>(h->n, steps_per_launch, group_rows, h->dev, &chunk_w);
     if (chunk <= 0) return record_hip(hipErrorInvalidValue, "occupancy query for the marching kernel");
     HIPCHK(hipStreamSynchronize(h->stream));
     drop_graphs(h);
@@ -941,21 +941,23 @@ int dmrt_set_temporal_march(dmrt_cavity* h, int steps_per_launch, int group_rows
     if (steps_per_launch <= 4 && !valid_temporal(steps_per_launch, h->t_rows)) h->t_rows = 10;
     h->march = group_rows;
     h->march_chunk = std::min(chunk, h->n);
+    h->march_chunk_w = std::min(std::max(chunk_w, 1), h->n);
     // shapes for the launches of fewer steps that end a count (the same
     // wave rows per group where the kernel has them, else the most)
-    for (int k = 0; k < 8; ++k) h->march_rem_B[k] = h->march_rem_chunk[k] = 0;
+    for (int k = 0; k < 8; ++k) h->march_rem_B[k] = h->march_rem_chunk[k] = h->march_rem_chunk_w[k] = 0;
     for (int k = 2; k < steps_per_launch; ++k) {
         int bk = valid_march(k, group_rows, int(h->esz)) ? group_rows : 0;
         for (int b = 8; b >= 1 && !bk; --b)
             if (valid_march(k, b, int(h->esz))) bk = b;
         if (!bk) continue;
-        int ck = chunk_rows;
+        int ck = chunk_rows, ckw = chunk_rows;
         if (ck == 0)
-            ck = h->esz == sizeof(double) ? march_chunk_auto<double>(h->n, k, bk, h->dev)
-                                          : march_chunk_auto<float>(h->n, k, bk, h->dev);
+            ck = h->esz == sizeof(double) ? march_chunk_auto<double>(h->n, k, bk, h->dev, &ckw)
+                                          : march_chunk_auto<float>(h->n, k, bk, h->dev, &ckw);
         if (ck <= 0) continue;
         h->march_rem_B[k] = bk;
         h->march_rem_chunk[k] = std::min(ck, h->n);
+        h->march_rem_chunk_w[k] = std::min(std::max(ckw, 1), h->n);
     }
     return DMRT_OK;
 }

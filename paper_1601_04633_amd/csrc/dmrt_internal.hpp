@@ -90,6 +90,9 @@ struct dmrt_cavity {
     // marching launches of fewer steps that end a count which is not a
     // multiple of K: wave rows per group (0: none) and chunk rows, by steps
     int march_rem_B[8] = {}, march_rem_chunk[8] = {};   // indexed by steps, up to kMaxK
+    // chunk rows of the two bands that hold the side walls (shorter where
+    // the chunk is chosen automatically: their rows cost more)
+    int march_chunk_w = 0, march_rem_chunk_w[8] = {};
     int adj_temporal = 1, adj_rows = 10;   // the same for the adjoint's backward launches
     int graph_flips[2] = {0, 0};      // copy changes made by one replay of graph[p]
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -158,10 +161,18 @@ inline bool valid_march(int k, int b, int esz)
     return false;
 }
 
+// A row of a band that holds a side wall costs this much more than an
+// interior row (the wall links' own-node reads and selects, the wall
+// temperature; measured at 1024^2 with six steps per launch).
+constexpr double kWallRowCost = 1.08;
+
 // Rows per workgroup of the row-marching kernel that leave every workgroup
-// of one launch resident at once (at least 1 row).
+// of one launch resident at once (at least 1 row), and in *chunk_w those of
+// the two side-wall bands: shorter, so that their workgroups take about as
+// long as the others (a sweep of c rows takes c plus 2(K - 1) halo and
+// (K - 1)(B + 1) pipeline rows), as far as the resident slots allow.
 template <typename real>
-int march_chunk_auto(int n, int K, int B, int dev)
+int march_chunk_auto(int n, int K, int B, int dev, int* chunk_w = nullptr)
 {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
@@ -177,8 +188,20 @@ int march_chunk_auto(int n, int K, int B, int dev)
     if (per_cu <= 0) return -1;
     const int W = kFootW - 2 * (K - 1);
     const int tiles_x = (n + W - 1) / W;
-    const int chunks = std::max(1, per_cu * cus / tiles_x);
-    return std::max(1, (n + chunks - 1) / chunks);
+    const int slots = per_cu * cus;
+    const int chunks = std::max(1, slots / tiles_x);
+    const int chunk = std::max(1, (n + chunks - 1) / chunks);
+    if (chunk_w) {
+        int cw = chunk;
+        if (tiles_x >= 3) {
+            const int L = 2 * (K - 1) + (K - 1) * (B + 1);
+            cw = std::max(1, std::min(chunk, int((chunk + L) / kWallRowCost - L + 0.5)));
+            const long ni = long(tiles_x - 2) * ((n + chunk - 1) / chunk);
+            while (cw < chunk && ni + 2L * ((n + cw - 1) / cw) > slots) ++cw;
+        }
+        *chunk_w = cw;
+    }
+    return chunk;
 }
 
 // Workgroups to append to a stepping launch of `threads` threads per
@@ -203,6 +226,7 @@ int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
     const bool rem = k > 0 && k != h->temporal;
     const int K = rem ? k : h->temporal, B = rem ? h->march_rem_B[k] : h->march;
     const int chunk = rem ? h->march_rem_chunk[k] : h->march_chunk;
+    const int chunk_w = rem ? h->march_rem_chunk_w[k] : h->march_chunk_w;
     StepArgs<real> A;
     A.fin = fin; A.gin = gin; A.fout = fout; A.gout = gout;
     A.samp = samp; A.samp_mask = samp_mask;
@@ -210,7 +234,10 @@ int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
     A.n = h->n; A.pitch = h->pitch; A.plane = h->plane;
     const int W = kFootW - 2 * (K - 1);
     A.tiles_x = (h->n + W - 1) / W;
-    A.tiles = A.tiles_x * ((h->n + chunk - 1) / chunk);
+    // the bands without a side wall, then the one or two that hold them
+    // (stepm_body's order)
+    const int nb = A.tiles_x, nw = std::min(nb, 2);
+    A.tiles = (nb - nw) * ((h->n + chunk - 1) / chunk) + nw * ((h->n + chunk_w - 1) / chunk_w);
     A.xcd_remap = h->xcd_remap;
     A.c = make_coef<real>(h->p, h->d);
     int nblocks = A.tiles;
@@ -221,9 +248,11 @@ int launch_stepm(const dmrt_cavity* h, hipStream_t s, const real* fin, const rea
     if constexpr (march_lds_bytes(KK, BB, sizeof(real)) <= kLdsBytes)                     \
         if (K == KK && B == BB) {                                                         \
             if (samp_mask)                                                                \
-                hipLaunchKernelGGL((stepm_samp_kernel<real, KK, BB>), grid, block, 0, s, A, chunk); \
+                hipLaunchKernelGGL((stepm_samp_kernel<real, KK, BB>), grid, block, 0, s, A, chunk, \
+                                   chunk_w);                                              \
             else                                                                          \
-                hipLaunchKernelGGL((stepm_kernel<real, KK, BB>), grid, block, 0, s, A, chunk); \
+                hipLaunchKernelGGL((stepm_kernel<real, KK, BB>), grid, block, 0, s, A, chunk,  \
+                                   chunk_w);                                              \
             return record_hip(hipGetLastError(), "stepm_kernel");                        \
         }
     DMRT_FOR_EACH_KB(DMRT_KB)
