@@ -91,3 +91,75 @@ def test_a_shorter_ring_or_lag_fails():
     assert not broken(100, 4, 3, 37, 2, 4)     # the kernel's choice passes
     assert broken(100, 4, 3, 37, 1, 4)         # ring one row short
     assert broken(100, 4, 3, 37, 2, 3)         # groups one row too close
+
+
+# The launch's tiles (stepm_body): the bands without a side wall first,
+# chunk rows each, chunk row by chunk row, then the one or two bands that
+# hold the side walls, chunk_w rows each, left and right in turn.
+def tile_rows(n, K, chunk, chunk_w):
+    W = 64 - 2 * (K - 1)
+    nb = (n + W - 1) // W
+    nw = min(nb, 2)
+    nch = (n + chunk - 1) // chunk
+    tiles = (nb - nw) * nch + nw * ((n + chunk_w - 1) // chunk_w)
+    ni = (nb - 2) * nch if nb > 2 else 0
+    out = []
+    for tile in range(tiles):
+        if tile < ni:
+            tyt = tile // (nb - 2)
+            txt = 1 + (tile - tyt * (nb - 2))
+            ch = chunk
+        else:
+            t = tile - ni
+            tyt = t if nb == 1 else t >> 1
+            txt = 0 if nb == 1 else (nb - 1 if t & 1 else 0)
+            ch = chunk_w
+        out.append((txt, tyt * ch, min(tyt * ch + ch, n)))
+    return nb, out
+
+
+# The automatic chunks (march_chunk_auto): the shortest chunk that keeps
+# every workgroup resident, and for the side-wall bands the chunk whose
+# sweep, at 1.08 times the cost per row, takes about as long, lengthened
+# until the launch fits the slots again.
+def auto_chunks(n, K, B, slots, wall_cost=1.08):
+    W = 64 - 2 * (K - 1)
+    nb = (n + W - 1) // W
+    chunks = max(1, slots // nb)
+    chunk = max(1, (n + chunks - 1) // chunks)
+    cw = chunk
+    if nb >= 3:
+        L = 2 * (K - 1) + (K - 1) * (B + 1)
+        cw = max(1, min(chunk, int((chunk + L) / wall_cost - L + 0.5)))
+        ni = (nb - 2) * ((n + chunk - 1) // chunk)
+        while cw < chunk and ni + 2 * ((n + cw - 1) // cw) > slots:
+            cw += 1
+    return chunk, cw
+
+
+@pytest.mark.parametrize("K", [2, 3, 4, 6])
+def test_tiles_cover_every_band_and_row_once(K):
+    for n in [4, 5, 7, 16, 54, 55, 60, 108, 109, 257, 1024, 2048]:
+        for chunk in sorted({1, 3, 7, 37, 40, n}):
+            for cw in sorted({1, 5, 35, chunk}):
+                if cw > chunk or chunk > n:
+                    continue
+                nb, rows = tile_rows(n, K, chunk, cw)
+                seen = {}
+                for txt, y0, y1 in rows:
+                    assert 0 <= txt < nb and 0 <= y0 < y1 <= n
+                    for y in range(y0, y1):
+                        seen[(txt, y)] = seen.get((txt, y), 0) + 1
+                assert len(seen) == nb * n and set(seen.values()) == {1}, (n, K, chunk, cw)
+
+
+def test_wall_band_chunks_keep_every_workgroup_resident():
+    assert auto_chunks(1024, 6, 2, 512) == (40, 35)     # 17 x 26 + 2 x 30 = 502 workgroups
+    for K, B in PAIRS:
+        for n in [64, 100, 257, 512, 1024, 1536, 2048, 4096]:
+            for slots in [256, 512, 768]:
+                chunk, cw = auto_chunks(n, K, B, slots)
+                assert 1 <= cw <= chunk
+                nb, rows = tile_rows(n, K, chunk, cw)
+                base = len(tile_rows(n, K, chunk, chunk)[1])
+                assert len(rows) <= max(slots, base), (n, K, B, slots)
