@@ -47,7 +47,7 @@ TRAFFIC_FILES = {
     ("stepm_kernel<float, 4, 3>", 1024): "stepm_kernel_K4_B3_cavity_1024_fp32_traffic.json",
     ("stepm_kernel<float, 6, 2>", 1024): "stepm_kernel_K6_B2_cavity_1024_fp32_traffic.json",
     ("stepm_kernel<float, 6, 2>", 2048): "stepm_kernel_K6_B2_cavity_2048_fp32_traffic.json",
-    ("stepm_kernel<double, 4, 4>", 1024): "stepm_kernel_K4_B4_cavity_1024_fp64_traffic.json",
+    ("stepm_kernel<double, 6, 2>", 1024): "stepm_kernel_K6_B2_cavity_1024_fp64_traffic.json",
 }
 # launch configuration timed by default (the fastest for this workload on
 # MI355X): six steps per launch, workgroups of 6 x 2 wavefronts marching
@@ -567,8 +567,8 @@ def main():
 
         log("extra: fp32 row-marching with four steps per launch (4 x 3 wavefronts)")
         extra("fp32_march_K4_B3", n, prec, max(args.steps // 5, 2000), 500, ("march", 4, 3, 0))
-        log("extra: fp64 same cavity, row-marching (4 steps, 4 x 4 wavefronts) and tile (4 steps, 16 rows)")
-        extra("fp64_march_K4_B4", n, "fp64", max(args.steps // 10, 1200), 600, ("march", 4, 4, 0))
+        log("extra: fp64 same cavity, row-marching (6 steps, 6 x 2 wavefronts) and tile (4 steps, 16 rows)")
+        extra("fp64_march_K6_B2", n, "fp64", max(args.steps // 10, 1200), 600, ("march", 6, 2, 0))
         extra("fp64_tile_K4_R16", n, "fp64", max(args.steps // 10, 1200), 600, (4, 16))
         log("extra: fp32 tile kernel (4 steps, 16 rows) and single steps")
         extra("fp32_tile_K4_R16", n, prec, max(args.steps // 5, 2000), 500, (4, 16))
