@@ -52,9 +52,9 @@ TRAFFIC_FILES = {
 # launch configuration timed by default (the fastest for this workload on
 # MI355X): six steps per launch, workgroups of 6 x 2 wavefronts marching
 # up chunks of rows (chunk length chosen to keep one launch resident),
-# die-aware order, graphs of 60 steps
+# die-aware order, graphs of 240 steps (a multiple of every steps per launch)
 DEFAULT_TEMPORAL = ("march", 6, 2, 0)
-DEFAULT_LAUNCH = (256, 1, 1, 60)
+DEFAULT_LAUNCH = (256, 1, 1, 240)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1601_04633_amd", "csrc", f)
                   for f in ("dmrt_device.hpp",)]
 
